@@ -1,0 +1,104 @@
+"""Write tests/golden/workloads.json: the choices that need a count, and the
+expected values the tests compare against.  Calls only the CPU oracle.
+
+    python tests/golden/make_workloads.py
+
+Choices (the readings of the workload descriptions):
+  single_small   g = (11,13,17,23), n = 10000.
+  single_large   d = 6 generators from SplitMix64(seed), distinct, uniform in
+                 [20,200], gcd 1, drawn order, n = 100000; seed = the first of
+                 0,1,2,... whose |Z| lies in [1e10, 1e11].  Store mode keeps the
+                 5e8 lex-smallest elements.
+  length_set     10 distinct generators uniform in [50,500] with gcd 1 from
+                 SplitMix64(0), then a copy of one of them; n = the smallest n
+                 with |Z(n)| >= 1e11.
+  batch          4096 queries; query i draws from SplitMix64(i-th output of
+                 SplitMix64(master)) and draws again while |Z| > 1e8.
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import fzinputs  # noqa: E402
+import oracle  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
+
+BATCH_MASTER_SEED = 20240513
+BATCH_QUERIES = 4096
+BATCH_CAP = 10**8
+
+
+def single_small():
+    w = fzinputs.single_small()
+    n, g = w["n"], w["g"]
+    h, lo, hi = oracle.hist(n, g)
+    st = oracle.store(n, g)
+    target = n // max(g) + 1
+    return dict(n=n, g=g, count=oracle.dp_count(n, g), count_by_walk=oracle.count(n, g),
+                min_len=lo, max_len=hi, nonzero_bins=int(np.count_nonzero(h)),
+                exists_target=target, exists=oracle.exists(n, g, target),
+                first=[int(x) for x in st[0]], last=[int(x) for x in st[-1]])
+
+
+def single_large():
+    n = 100000
+    for seed in range(1000):
+        g = fzinputs.single_large_generators(seed)
+        c = oracle.dp_count(n, g)
+        if 10**10 <= c <= 10**11:
+            return dict(seed=seed, n=n, g=g, count=c, store_max_tuples=5 * 10**8)
+    raise RuntimeError("no seed found")
+
+
+def length_set():
+    seed = 0
+    g = fzinputs.length_set_generators(seed)
+    series = oracle.dp_series(60000, g)
+    idx = np.nonzero(series >= 10**11)[0]
+    n = int(idx[0])
+    return dict(seed=seed, n=n, g=g, count=int(series[n]), nbins=n // min(g) + 1)
+
+
+def batch():
+    seeds = fzinputs.query_seeds(BATCH_MASTER_SEED, BATCH_QUERIES)
+    queries = []
+    redraws = 0
+    for s in seeds:
+        rng = fzinputs.SplitMix64(s)
+        while True:
+            q = fzinputs.draw_query(rng)
+            try:
+                c = oracle.dp_count(q["n"], q["g"])
+            except OverflowError:  # |Z| >= 2^64 - 1: far above the cap
+                c = None
+            if c is not None and c <= BATCH_CAP:
+                break
+            redraws += 1
+        q["count"] = c
+        queries.append(q)
+    return dict(master_seed=BATCH_MASTER_SEED, cap=BATCH_CAP, redraws=redraws, queries=queries)
+
+
+def main():
+    t0 = time.time()
+    out = dict(
+        note="written by tests/golden/make_workloads.py from the CPU oracle; do not edit",
+        single_small=single_small(),
+        single_large=single_large(),
+        length_set=length_set(),
+        batch=batch(),
+    )
+    with open(OUT, "w") as f:
+        json.dump(out, f, separators=(",", ":"))
+    print(f"wrote {OUT} in {time.time() - t0:.1f}s")
+
+
+if __name__ == "__main__":
+    main()
