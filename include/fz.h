@@ -1,0 +1,156 @@
+/*
+ * fz.h -- libfz: bounded lexicographic enumeration of factorization sets on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The factorization set of an element n with respect to generators g_1..g_d
+ * (paper Sec. 1) is
+ *
+ *     Z(n, g) = { (a_1, ..., a_d) in N^d : a_1 g_1 + ... + a_d g_d = n }.
+ *
+ * Generators may come in any order and may repeat (footnote to Sec. 1).  The
+ * caller's order fixes the lexicographic order of every output, and two equal
+ * generators are two distinct coordinates.
+ *
+ * Every call enumerates Z on the GPU.  The lex-ordered set is cut into
+ * disjoint bounded slices (Sec. 4); wavefronts walk their slices with the
+ * successor of Alg. 3.1 and its modulo skip (Sec. 3.2.4) and feed one
+ * consumer (Sec. 2): a counter, a length histogram, a predicate or a store.
+ * Slice bounds come from ranks: the set is counted by a dynamic-programming
+ * table on the device and each bound is the element of a chosen rank.
+ *
+ * Conventions shared by every entry point
+ *   n, g, d   the element, a HOST pointer to d generators (read during the
+ *             call only, never retained), and the dimension.
+ *   limits    1 <= d <= FZ_MAX_D; every g_i >= 1; n + max_i g_i < 2^31;
+ *             n < 2^30 when d <= 2; g_d <= FZ_MAX_LAST_GEN.  Breaking one
+ *             returns FZ_EINVAL (d, g, NULL pointers) or FZ_EOVERFLOW (sizes)
+ *             or FZ_E2BIG (g_d), and no output is written.
+ *   counts    exact unsigned 64-bit; a set with 2^64 - 1 or more elements
+ *             is FZ_EOVERFLOW.
+ *   errors    a negative status; no output argument is written unless the
+ *             entry point says otherwise.  FZ_EDEVICE: a HIP call failed (no
+ *             GPU, launch failure).  FZ_EINTERNAL: the per-slice element
+ *             counts disagreed with the ranks of the slice bounds (a
+ *             self-check that never fires on a correct build).
+ *   device    the current HIP device of the calling thread.  Calls are
+ *             synchronous and thread-safe: they are serialized per process.
+ *   memory    device scratch (count tables, slice bounds, per-workgroup
+ *             partial results) belongs to the library, which keeps it cached
+ *             between calls and frees it at process exit.
+ *   empty Z   is not an error: count 0, no rows, found 0.
+ *   n = 0     Z holds exactly one element, (0, ..., 0), of length 0.
+ */
+#ifndef FZ_H
+#define FZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FZ_MAX_D 16
+#define FZ_MAX_LAST_GEN (1u << 24)
+
+typedef enum {
+    FZ_OK = 0,
+    FZ_TRUNCATED = 1,   /* fz_enumerate*: fewer rows than |Z| were asked for */
+    FZ_EINVAL = -1,
+    FZ_EOVERFLOW = -2,
+    FZ_ENOMEM = -3,
+    FZ_EDEVICE = -4,
+    FZ_E2BIG = -5,
+    FZ_EINTERNAL = -6
+} fz_status;
+
+/* |Z(n, g)| into *count.  Each element is visited by the successor and
+ * counted (Sec. 2, the counting consumer). */
+int fz_count(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count);
+
+/* Number of bins a length histogram of Z(n, g) needs: n / min_i g_i + 1
+ * (every element has length sum_i a_i <= n / min g).  0 for invalid input. */
+uint64_t fz_length_bins(uint64_t n, const uint32_t *g, uint32_t d);
+
+/* Length histogram: bins[l] = #{a in Z : a_1 + ... + a_d = l} for
+ * l < nbins (host array of nbins words, nbins >= fz_length_bins(...), else
+ * FZ_EINVAL).  *min_len / *max_len: the shortest and longest length that
+ * occurs (UINT64_MAX and 0 when Z is empty).  The set of lengths of an
+ * element is the classic "length set" of numerical semigroups; this consumer
+ * is not in the paper, whose Sec. 2 names counters, predicates and stores. */
+int fz_length_hist(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *bins,
+                   uint64_t nbins, uint64_t *min_len, uint64_t *max_len);
+
+/* Predicate consumer (Sec. 2): *found = 1 if some a in Z has length
+ * a_1 + ... + a_d == target_len, else 0.  Workers stop early once one
+ * wavefront has found a witness. */
+int fz_exists(uint64_t n, const uint32_t *g, uint32_t d, uint64_t target_len,
+              int *found);
+
+/* Store consumer (Sec. 2): the min(|Z|, max_tuples) lex-smallest elements of
+ * Z in ascending lexicographic order (the reverse of the paper's descending
+ * walk, Sec. 3.2), row-major into the HOST buffer out[max_tuples][d] (uint32
+ * coordinates).  *total = |Z|, *written = rows written.  Returns FZ_OK, or
+ * FZ_TRUNCATED when max_tuples < |Z| (a success: the rows are valid). */
+int fz_enumerate(uint64_t n, const uint32_t *g, uint32_t d, uint32_t *out,
+                 uint64_t max_tuples, uint64_t *total, uint64_t *written);
+
+/* As fz_enumerate, but d_out is a DEVICE pointer (for instance the data of a
+ * torch tensor) on the current device, and the work is queued on `stream`
+ * (a hipStream_t; NULL for the library's own stream).  The call waits for
+ * that stream before it returns *total and *written. */
+int fz_enumerate_device(uint64_t n, const uint32_t *g, uint32_t d,
+                        uint32_t *d_out, uint64_t max_tuples, uint64_t *total,
+                        uint64_t *written, void *stream);
+
+/* As fz_count, queued on `stream` (a hipStream_t, NULL: the library's own);
+ * waits for it before returning. */
+int fz_count_stream(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
+                    void *stream);
+
+/* The slice-bound primitive (Sec. 4, bounds; done here by ranks): for each
+ * of the nranks ranks (0-based, host array), the element of that rank in
+ * ascending lex order, row-major into the HOST buffer out[nranks][d].  A
+ * rank >= |Z| gives FZ_EINVAL and writes nothing. */
+int fz_unrank(uint64_t n, const uint32_t *g, uint32_t d, const uint64_t *ranks,
+              uint64_t nranks, uint32_t *out);
+
+/* Work statistics of the last successful enumeration on this device:
+ * slices used, rows walked (one row = one prefix a_1..a_{d-3}), prefixes
+ * (a_1..a_{d-2}) visited by lanes, candidate steps taken (one per element
+ * visited plus one failing test per prefix), and elements. */
+typedef struct {
+    uint64_t slices;
+    uint64_t rows;
+    uint64_t prefixes;
+    uint64_t candidates;
+    uint64_t elements;
+} fz_stats;
+int fz_last_stats(fz_stats *out);
+
+/* Tuning knobs (0 restores the default): "slices_per_wave" (slices cut per
+ * resident wavefront), "workgroups_per_cu" (persistent workgroups per compute
+ * unit).  FZ_EINVAL for an unknown key or a negative value. */
+int fz_config_set(const char *key, int64_t value);
+
+/* Kernel timing with HIP events on the launch stream.  fz_profile_enable(1)
+ * starts recording (it adds no synchronization of its own); fz_profile_read
+ * gives the summed milliseconds and launch count of one kernel ("dp",
+ * "restab", "slices", "enum.count", "enum.hist", "enum.exists", "enum.store",
+ * "finalize", "unrank") since the last reset. */
+int fz_profile_enable(int on);
+int fz_profile_reset(void);
+int fz_profile_read(const char *kernel, double *total_ms, uint64_t *launches);
+
+/* The HIP call that produced this thread's last FZ_EDEVICE / FZ_ENOMEM, with
+ * the HIP error text ("" if none).  The string is owned by the library and
+ * stays valid until the thread's next failing call. */
+const char *fz_last_error(void);
+
+/* Static description of a status code. */
+const char *fz_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FZ_H */

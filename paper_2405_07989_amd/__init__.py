@@ -1,0 +1,200 @@
+"""Python binding of libfz (include/fz.h): argument marshalling only.
+
+Every step of the enumeration runs in the HIP kernels of ``libfz.so``; this
+module converts Python integers, numpy arrays and torch tensors to the C ABI
+and status codes to exceptions.  Importing it fails loudly when the library
+has not been built (``python paper_2405_07989_amd/build.py``); there is no
+fallback of any kind.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfz.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "fz.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libfz.so not found at {LIB_PATH}: build it with `python paper_2405_07989_amd/build.py`")
+
+# One HIP runtime per process: torch ships its own libamdhip64.so.7, and a
+# second copy loaded from /opt/rocm would not see the device torch holds (nor
+# share its pointers and streams).  Importing torch first makes the dynamic
+# loader bind libfz.so's libamdhip64.so.7 to the copy already in memory.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FZ_OK, FZ_TRUNCATED = 0, 1
+FZ_EINVAL, FZ_EOVERFLOW, FZ_ENOMEM, FZ_EDEVICE, FZ_E2BIG, FZ_EINTERNAL = -1, -2, -3, -4, -5, -6
+FZ_MAX_D = 16
+
+
+class FzError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        detail = ""
+        if status in (FZ_EDEVICE, FZ_ENOMEM):
+            detail = f" [{_lib.fz_last_error().decode()}]"
+        super().__init__(f"{what}: {_lib.fz_strerror(status).decode()} (status {status}){detail}")
+
+
+class fz_stats(ctypes.Structure):
+    _fields_ = [("slices", ctypes.c_uint64), ("rows", ctypes.c_uint64),
+                ("prefixes", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+                ("elements", ctypes.c_uint64)]
+
+
+_u64, _u32, _i64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_vp = ctypes.c_void_p
+
+_SIGS = {
+    "fz_count": (ctypes.c_int, [_u64, _u32p, _u32, _u64p]),
+    "fz_count_stream": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _vp]),
+    "fz_length_bins": (ctypes.c_uint64, [_u64, _u32p, _u32]),
+    "fz_length_hist": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _u64, _u64p, _u64p]),
+    "fz_exists": (ctypes.c_int, [_u64, _u32p, _u32, _u64, ctypes.POINTER(ctypes.c_int)]),
+    "fz_enumerate": (ctypes.c_int, [_u64, _u32p, _u32, _u32p, _u64, _u64p, _u64p]),
+    "fz_enumerate_device": (ctypes.c_int, [_u64, _u32p, _u32, _vp, _u64, _u64p, _u64p, _vp]),
+    "fz_unrank": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _u64, _u32p]),
+    "fz_last_stats": (ctypes.c_int, [ctypes.POINTER(fz_stats)]),
+    "fz_config_set": (ctypes.c_int, [ctypes.c_char_p, _i64]),
+    "fz_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "fz_profile_reset": (ctypes.c_int, []),
+    "fz_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), _u64p]),
+    "fz_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fz_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def exported_symbols_in_header() -> list[str]:
+    """Names of the functions include/fz.h declares."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|uint64_t|const char \*)\s*(fz_\w+)\s*\(", text, re.M)))
+
+
+def _gens(g):
+    arr = np.ascontiguousarray(np.asarray(g, dtype=np.uint32).reshape(-1))
+    return arr, arr.ctypes.data_as(_u32p)
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise FzError(rc, what)
+    return rc
+
+
+def count(n: int, g, stream=None) -> int:
+    """|Z(n, g)| (fz_count / fz_count_stream)."""
+    arr, gp = _gens(g)
+    out = ctypes.c_uint64(0)
+    if stream is None:
+        _check(_lib.fz_count(n, gp, len(arr), ctypes.byref(out)), "fz_count")
+    else:
+        _check(_lib.fz_count_stream(n, gp, len(arr), ctypes.byref(out), _vp(stream)), "fz_count_stream")
+    return out.value
+
+
+def length_bins(n: int, g) -> int:
+    arr, gp = _gens(g)
+    return int(_lib.fz_length_bins(n, gp, len(arr)))
+
+
+def length_hist(n: int, g, nbins: int | None = None):
+    """(bins, min_len, max_len); min/max are None when Z is empty."""
+    arr, gp = _gens(g)
+    nb = length_bins(n, g) if nbins is None else nbins
+    bins = np.zeros(max(nb, 1), dtype=np.uint64)
+    lo, hi = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(_lib.fz_length_hist(n, gp, len(arr), bins.ctypes.data_as(_u64p), nb,
+                               ctypes.byref(lo), ctypes.byref(hi)), "fz_length_hist")
+    if lo.value == 2**64 - 1:
+        return bins[:nb], None, None
+    return bins[:nb], lo.value, hi.value
+
+
+def exists(n: int, g, target_len: int) -> bool:
+    arr, gp = _gens(g)
+    f = ctypes.c_int(0)
+    _check(_lib.fz_exists(n, gp, len(arr), target_len, ctypes.byref(f)), "fz_exists")
+    return bool(f.value)
+
+
+def enumerate_host(n: int, g, max_tuples: int):
+    """The min(|Z|, max_tuples) lex-smallest elements as a numpy array
+    (fz_enumerate); returns (rows, total)."""
+    arr, gp = _gens(g)
+    d = len(arr)
+    out = np.zeros((max(max_tuples, 1), d), dtype=np.uint32)
+    total, written = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(_lib.fz_enumerate(n, gp, d, out.ctypes.data_as(_u32p), max_tuples,
+                             ctypes.byref(total), ctypes.byref(written)), "fz_enumerate")
+    return out[: written.value], total.value
+
+
+def enumerate_device(n: int, g, out, max_tuples: int | None = None, stream=None):
+    """Write the lex-smallest rows into ``out`` (a contiguous torch.int32 or
+    uint32-compatible CUDA tensor of shape [rows, d]) on the current device
+    (fz_enumerate_device).  Returns (total, written)."""
+    arr, gp = _gens(g)
+    d = len(arr)
+    if out.dim() != 2 or out.shape[1] != d or not out.is_contiguous() or out.element_size() != 4:
+        raise ValueError("out must be a contiguous [rows, d] tensor of 32-bit integers")
+    cap = out.shape[0] if max_tuples is None else max_tuples
+    if cap > out.shape[0]:
+        raise ValueError("max_tuples exceeds the rows of out")
+    total, written = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(_lib.fz_enumerate_device(n, gp, d, _vp(out.data_ptr()), cap, ctypes.byref(total),
+                                    ctypes.byref(written), _vp(stream) if stream else None),
+           "fz_enumerate_device")
+    return total.value, written.value
+
+
+def unrank(n: int, g, ranks):
+    """Element of each rank in ascending lex order (fz_unrank)."""
+    arr, gp = _gens(g)
+    r = np.ascontiguousarray(np.asarray(ranks, dtype=np.uint64).reshape(-1))
+    out = np.zeros((max(len(r), 1), len(arr)), dtype=np.uint32)
+    _check(_lib.fz_unrank(n, gp, len(arr), r.ctypes.data_as(_u64p), len(r), out.ctypes.data_as(_u32p)),
+           "fz_unrank")
+    return out[: len(r)]
+
+
+def last_stats() -> dict:
+    s = fz_stats()
+    _check(_lib.fz_last_stats(ctypes.byref(s)), "fz_last_stats")
+    return {k: getattr(s, k) for k, _ in fz_stats._fields_}
+
+
+def config_set(key: str, value: int) -> None:
+    _check(_lib.fz_config_set(key.encode(), value), f"fz_config_set({key})")
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.fz_profile_enable(1 if on else 0), "fz_profile_enable")
+
+
+def profile_reset() -> None:
+    _check(_lib.fz_profile_reset(), "fz_profile_reset")
+
+
+def profile_read(kernel: str):
+    """(total_ms, launches) of one kernel since the last reset."""
+    ms, n = ctypes.c_double(0), ctypes.c_uint64(0)
+    _check(_lib.fz_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)), "fz_profile_read")
+    return ms.value, n.value
+
+
+def strerror(status: int) -> str:
+    return _lib.fz_strerror(status).decode()

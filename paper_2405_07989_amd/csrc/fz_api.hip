@@ -1,0 +1,555 @@
+// fz_api.hip -- libfz host engine: validation and normalization of a query,
+// planning, device scratch, kernel launches and the C ABI of include/fz.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fz.h"
+#include "fz_internal.h"
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr uint32_t kDefaultSlicesPerWave = 4;
+constexpr uint32_t kDefaultWgPerCu = 8;
+constexpr uint32_t kMaxSlices = 1u << 22;
+constexpr size_t kLdsHistBudget = 64 * 1024;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct Ctx {
+    bool ready = false;
+    int device = -1;
+    int cus = 0;
+    hipStream_t stream = nullptr;
+    FzCtl *host_ctl = nullptr; // pinned
+    DevBuf S, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out, sentry;
+    fz_stats last{};
+};
+
+std::mutex g_mu;
+Ctx g_ctx[kMaxDevices];
+uint32_t g_slices_per_wave = 0;
+uint32_t g_wg_per_cu = 0;
+
+struct ProfEntry {
+    double ms = 0;
+    uint64_t n = 0;
+};
+bool g_prof = false;
+std::map<std::string, ProfEntry> g_prof_stats;
+struct PendingEv {
+    const char *name;
+    hipEvent_t a, b;
+};
+std::vector<PendingEv> g_pending;
+
+thread_local char g_err_msg[256] = "";
+
+int dev_err_at(hipError_t e, const char *what, int line)
+{
+    std::snprintf(g_err_msg, sizeof g_err_msg, "%s (line %d): %s (%d)", what, line,
+                  hipGetErrorString(e), (int)e);
+    if (e == hipErrorOutOfMemory) return FZ_ENOMEM;
+    return FZ_EDEVICE;
+}
+
+hipError_t ensure(DevBuf &b, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    if (bytes <= b.cap) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = std::max(bytes, (size_t)4096);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        return e;
+    }
+    b.cap = want;
+    return hipSuccess;
+}
+
+#define FZ_TRY(expr)                                                                                \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            return dev_err_at(e_, #expr, __LINE__);                                                \
+        }                                                                                          \
+    } while (0)
+
+#define FZ_LAUNCH(name, stream, call)                                                              \
+    do {                                                                                           \
+        hipEvent_t ev_;                                                                            \
+        prof_begin(stream, &ev_);                                                                  \
+        hipError_t e_ = (call);                                                                    \
+        prof_end(stream, name, ev_);                                                               \
+        if (e_ != hipSuccess) {                                                                    \
+            (void)hipGetLastError();                                                               \
+            return dev_err_at(e_, name, __LINE__);                                                 \
+        }                                                                                          \
+    } while (0)
+
+int get_ctx(Ctx **out)
+{
+    // Drop an error another library may have left in this thread's HIP
+    // state, so that the launch checks below see only this call's errors.
+    (void)hipGetLastError();
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return dev_err_at(e == hipSuccess ? hipErrorInvalidDevice : e, "hipGetDevice", __LINE__);
+    }
+    Ctx &c = g_ctx[dev];
+    if (!c.ready) {
+        int cus = 0;
+        FZ_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        FZ_TRY(hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking));
+        FZ_TRY(hipHostMalloc((void **)&c.host_ctl, sizeof(FzCtl), hipHostMallocDefault));
+        c.device = dev;
+        c.cus = cus;
+        c.ready = true;
+    }
+    *out = &c;
+    return FZ_OK;
+}
+
+uint64_t gcd64(uint64_t a, uint64_t b)
+{
+    while (b) {
+        uint64_t t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// inverse of a modulo m (gcd(a, m) = 1), extended Euclid; 0 when m == 1
+uint32_t modinv(uint64_t a, uint64_t m)
+{
+    if (m == 1) return 0;
+    int64_t t = 0, nt = 1;
+    int64_t r = (int64_t)m, nr = (int64_t)(a % m);
+    while (nr) {
+        int64_t q = r / nr;
+        int64_t tmp = t - q * nt;
+        t = nt;
+        nt = tmp;
+        tmp = r - q * nr;
+        r = nr;
+        nr = tmp;
+    }
+    if (t < 0) t += (int64_t)m;
+    return (uint32_t)t;
+}
+
+// Granlund-Montgomery (1994) Fig. 4.1 constants for divisor d >= 1.
+FzFastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    FzFastDiv f;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+    f.s1 = l < 1 ? l : 1;
+    f.s2 = l > 0 ? l - 1 : 0;
+    f.d = d;
+    return f;
+}
+
+// Validation and normalization (all limits of include/fz.h).
+int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *P)
+{
+    if (g == nullptr || d == 0 || d > FZ_MAX_D) return FZ_EINVAL;
+    uint64_t maxg = 0, ming = UINT64_MAX;
+    for (uint32_t i = 0; i < d; ++i) {
+        if (g[i] == 0) return FZ_EINVAL;
+        maxg = std::max<uint64_t>(maxg, g[i]);
+        ming = std::min<uint64_t>(ming, g[i]);
+    }
+    if (n + maxg >= (1ull << 31)) return FZ_EOVERFLOW;
+    if (d <= 2 && n >= (1ull << 30)) return FZ_EOVERFLOW;
+    if (g[d - 1] > FZ_MAX_LAST_GEN) return FZ_E2BIG;
+    std::memset(P, 0, sizeof *P);
+    P->n = (uint32_t)n;
+    P->d_user = d;
+    P->pad = d < 3 ? 3 - d : 0;
+    P->d = d + P->pad;
+    for (uint32_t i = 0; i < P->pad; ++i) P->g[i] = (uint32_t)n + 1; // virtual: always 0
+    for (uint32_t i = 0; i < d; ++i) P->g[P->pad + i] = g[i];
+    const uint32_t D3 = P->d;
+    P->G2 = P->g[D3 - 3];
+    P->A = P->g[D3 - 2];
+    P->B = P->g[D3 - 1];
+    P->D = (uint32_t)gcd64(P->A, P->B);
+    P->ord = P->B / P->D;
+    P->delta = P->A / P->D;
+    P->inv = modinv(P->delta % P->ord, P->ord);
+    P->mode = mode;
+    P->div_B = make_fastdiv(P->B);
+    P->div_delta = make_fastdiv(P->delta);
+    P->nbins = (uint32_t)(n / ming + 1);
+    P->stride = (uint32_t)n + 1;
+    P->target_len = 0;
+    P->max_tuples = UINT64_MAX;
+    return FZ_OK;
+}
+
+void prof_begin(hipStream_t s, hipEvent_t *ev)
+{
+    *ev = nullptr;
+    if (!g_prof) return;
+    if (hipEventCreate(ev) != hipSuccess) {
+        *ev = nullptr;
+        return;
+    }
+    hipEventRecord(*ev, s);
+}
+
+void prof_end(hipStream_t s, const char *name, hipEvent_t a)
+{
+    if (!g_prof || !a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) return;
+    hipEventRecord(b, s);
+    g_pending.push_back({name, a, b});
+}
+
+void prof_collect()
+{
+    for (auto &p : g_pending) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            auto &e = g_prof_stats[p.name];
+            e.ms += ms;
+            e.n += 1;
+        }
+        hipEventDestroy(p.a);
+        hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+}
+
+struct Launch {
+    uint32_t nwg;
+};
+
+// Sizes the scratch for plan P and fills the buffer table.
+int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
+{
+    const uint32_t wgcu = g_wg_per_cu ? g_wg_per_cu : kDefaultWgPerCu;
+    const uint32_t spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
+    const uint64_t waves = (uint64_t)c.cus * wgcu * (FZK_WG / FZK_WAVE);
+    P.n_slices = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(waves * spw, 1), kMaxSlices);
+    L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
+                                         (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
+    P.hist_in_lds =
+        (P.mode == FZM_HIST) && ((size_t)(FZK_WG / FZK_WAVE) * P.nbins * 4 <= kLdsHistBudget);
+    const uint64_t table_words = (uint64_t)(P.d - 1) * P.stride;
+    FZ_TRY(ensure(c.S, table_words * 8));
+    FZ_TRY(ensure(c.restab, (size_t)P.B * sizeof(int2)));
+    FZ_TRY(ensure(c.bounds, (size_t)(P.n_slices + 1) * (P.d - 2) * 4));
+    FZ_TRY(ensure(c.base, (size_t)(P.n_slices + 1) * 8));
+    FZ_TRY(ensure(c.recs, (size_t)P.n_slices * sizeof(FzSliceRec)));
+    FZ_TRY(ensure(c.ctl, sizeof(FzCtl)));
+    if (P.mode == FZM_HIST) {
+        FZ_TRY(ensure(c.hist, (size_t)P.nbins * 8));
+        if (P.hist_in_lds) FZ_TRY(ensure(c.hist_rows, (size_t)L.nwg * P.nbins * 8));
+    }
+    B.S = (uint64_t *)c.S.p;
+    B.restab = (int2 *)c.restab.p;
+    B.bounds = (uint32_t *)c.bounds.p;
+    B.base = (uint64_t *)c.base.p;
+    B.recs = (FzSliceRec *)c.recs.p;
+    B.ctl = (FzCtl *)c.ctl.p;
+    B.hist_rows = (uint64_t *)c.hist_rows.p;
+    B.hist = (uint64_t *)c.hist.p;
+    B.out = nullptr;
+    return FZ_OK;
+}
+
+// Queues the whole path for one query and waits: count table, residue table,
+// slice bounds, walker, finalize, control-block readback.
+int run_query(Ctx &c, FzPlan &P, FzBufs &B, const Launch &L, hipStream_t s)
+{
+    FZ_LAUNCH("dp", s, fzk_launch_dp(P, B, s));
+    FZ_LAUNCH("restab", s, fzk_launch_restab(P, B, s));
+    FZ_LAUNCH("slices", s, fzk_launch_slices(P, B, s));
+    static const char *const kEnumNames[] = {"enum.count", "enum.hist", "enum.exists",
+                                             "enum.store"};
+    FZ_LAUNCH(kEnumNames[P.mode & 3], s, fzk_launch_enum(P, B, L.nwg, s));
+    FZ_LAUNCH("finalize", s, fzk_launch_finalize(P, B, L.nwg, s));
+    FZ_TRY(hipMemcpyAsync(c.host_ctl, B.ctl, sizeof(FzCtl), hipMemcpyDeviceToHost, s));
+    FZ_TRY(hipStreamSynchronize(s));
+    prof_collect();
+    const FzCtl &h = *c.host_ctl;
+    if (h.status & FZS_OVERFLOW) return FZ_EOVERFLOW;
+    if (h.status & FZS_MISMATCH) return FZ_EINTERNAL;
+    c.last.slices = P.n_slices;
+    c.last.rows = h.rows;
+    c.last.prefixes = h.prefixes;
+    c.last.elements = h.count;
+    c.last.candidates = h.count + h.prefixes;
+    return FZ_OK;
+}
+
+int do_count(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count, void *stream)
+{
+    if (count == nullptr) return FZ_EINVAL;
+    FzPlan P;
+    int rc = make_plan(n, g, d, FZM_COUNT, &P);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    FzBufs B;
+    Launch L;
+    if ((rc = prepare(*c, P, B, L))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    if ((rc = run_query(*c, P, B, L, s))) return rc;
+    if (c->host_ctl->count != c->host_ctl->total) return FZ_EINTERNAL;
+    *count = c->host_ctl->count;
+    return FZ_OK;
+}
+
+int do_enumerate(uint64_t n, const uint32_t *g, uint32_t d, uint32_t *out, bool out_on_device,
+                 uint64_t max_tuples, uint64_t *total, uint64_t *written, void *stream)
+{
+    if (total == nullptr || written == nullptr) return FZ_EINVAL;
+    if (out == nullptr && max_tuples > 0) return FZ_EINVAL;
+    FzPlan P;
+    int rc = make_plan(n, g, d, FZM_STORE, &P);
+    if (rc) return rc;
+    P.max_tuples = max_tuples;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    FzBufs B;
+    Launch L;
+    if ((rc = prepare(*c, P, B, L))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    uint32_t *dev_out = out;
+    if (!out_on_device) {
+        // The host buffer needs a device staging copy of min(|Z|, max_tuples)
+        // rows: count first (one small readback), then size the staging.
+        FZ_LAUNCH("dp", s, fzk_launch_dp(P, B, s));
+        uint64_t N = 0;
+        FZ_TRY(hipMemcpyAsync(&N, B.S + P.n, 8, hipMemcpyDeviceToHost, s));
+        FZ_TRY(hipStreamSynchronize(s));
+        if (N == UINT64_MAX) return FZ_EOVERFLOW;
+        const uint64_t rows = std::min(N, max_tuples);
+        FZ_TRY(ensure(c->rows_out, rows * P.d_user * 4));
+        dev_out = (uint32_t *)c->rows_out.p;
+    }
+    B.out = dev_out;
+    if ((rc = run_query(*c, P, B, L, s))) return rc;
+    const FzCtl &h = *c->host_ctl;
+    const uint64_t N = h.total;
+    const uint64_t wr = std::min(N, max_tuples);
+    if (h.count != wr) return FZ_EINTERNAL;
+    if (!out_on_device && wr) {
+        FZ_TRY(hipMemcpyAsync(out, dev_out, wr * P.d_user * 4, hipMemcpyDeviceToHost, s));
+        FZ_TRY(hipStreamSynchronize(s));
+    }
+    *total = N;
+    *written = wr;
+    return wr < N ? FZ_TRUNCATED : FZ_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int fz_count(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count)
+{
+    return do_count(n, g, d, count, nullptr);
+}
+
+int fz_count_stream(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count, void *stream)
+{
+    return do_count(n, g, d, count, stream);
+}
+
+uint64_t fz_length_bins(uint64_t n, const uint32_t *g, uint32_t d)
+{
+    FzPlan P;
+    if (make_plan(n, g, d, FZM_HIST, &P)) return 0;
+    return P.nbins;
+}
+
+int fz_length_hist(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *bins, uint64_t nbins,
+                   uint64_t *min_len, uint64_t *max_len)
+{
+    if (bins == nullptr || min_len == nullptr || max_len == nullptr) return FZ_EINVAL;
+    FzPlan P;
+    int rc = make_plan(n, g, d, FZM_HIST, &P);
+    if (rc) return rc;
+    if (nbins < P.nbins) return FZ_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    FzBufs B;
+    Launch L;
+    if ((rc = prepare(*c, P, B, L))) return rc;
+    if ((rc = run_query(*c, P, B, L, c->stream))) return rc;
+    const FzCtl &h = *c->host_ctl;
+    if (h.count != h.total) return FZ_EINTERNAL;
+    std::vector<uint64_t> tmp(P.nbins);
+    FZ_TRY(hipMemcpy(tmp.data(), B.hist, (size_t)P.nbins * 8, hipMemcpyDeviceToHost));
+    uint64_t sum = 0;
+    for (uint64_t v : tmp) sum += v;
+    if (sum != h.count) return FZ_EINTERNAL;
+    std::memcpy(bins, tmp.data(), (size_t)P.nbins * 8);
+    for (uint64_t l = P.nbins; l < nbins; ++l) bins[l] = 0;
+    *min_len = h.count ? h.min_len : UINT64_MAX;
+    *max_len = h.count ? h.max_len : 0;
+    return FZ_OK;
+}
+
+int fz_exists(uint64_t n, const uint32_t *g, uint32_t d, uint64_t target_len, int *found)
+{
+    if (found == nullptr) return FZ_EINVAL;
+    FzPlan P;
+    int rc = make_plan(n, g, d, FZM_EXISTS, &P);
+    if (rc) return rc;
+    P.target_len = target_len;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    FzBufs B;
+    Launch L;
+    if ((rc = prepare(*c, P, B, L))) return rc;
+    if ((rc = run_query(*c, P, B, L, c->stream))) return rc;
+    const FzCtl &h = *c->host_ctl;
+    // Without a witness every slice ran to its end and must account for |Z|.
+    if (!h.found && h.count != h.total) return FZ_EINTERNAL;
+    *found = h.found ? 1 : 0;
+    return FZ_OK;
+}
+
+int fz_enumerate(uint64_t n, const uint32_t *g, uint32_t d, uint32_t *out, uint64_t max_tuples,
+                 uint64_t *total, uint64_t *written)
+{
+    return do_enumerate(n, g, d, out, false, max_tuples, total, written, nullptr);
+}
+
+int fz_enumerate_device(uint64_t n, const uint32_t *g, uint32_t d, uint32_t *d_out,
+                        uint64_t max_tuples, uint64_t *total, uint64_t *written, void *stream)
+{
+    return do_enumerate(n, g, d, d_out, true, max_tuples, total, written, stream);
+}
+
+int fz_unrank(uint64_t n, const uint32_t *g, uint32_t d, const uint64_t *ranks, uint64_t nranks,
+              uint32_t *out)
+{
+    if ((ranks == nullptr || out == nullptr) && nranks > 0) return FZ_EINVAL;
+    FzPlan P;
+    int rc = make_plan(n, g, d, FZM_COUNT, &P);
+    if (rc) return rc;
+    if (nranks == 0) return FZ_OK;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    if ((rc = get_ctx(&c))) return rc;
+    FzBufs B;
+    Launch L;
+    if ((rc = prepare(*c, P, B, L))) return rc;
+    FZ_TRY(ensure(c->ranks, nranks * 8));
+    FZ_TRY(ensure(c->rows_out, nranks * P.d_user * 4));
+    hipStream_t s = c->stream;
+    FZ_TRY(hipMemcpyAsync(c->ranks.p, ranks, nranks * 8, hipMemcpyHostToDevice, s));
+    FZ_LAUNCH("dp", s, fzk_launch_dp(P, B, s));
+    FZ_LAUNCH("slices", s, fzk_launch_slices(P, B, s)); // resets the control block
+    FZ_LAUNCH("unrank", s,
+              fzk_launch_unrank(P, B, (const uint64_t *)c->ranks.p, nranks,
+                                (uint32_t *)c->rows_out.p, s));
+    FZ_TRY(hipMemcpyAsync(c->host_ctl, B.ctl, sizeof(FzCtl), hipMemcpyDeviceToHost, s));
+    FZ_TRY(hipStreamSynchronize(s));
+    prof_collect();
+    if (c->host_ctl->status & FZS_OVERFLOW) return FZ_EOVERFLOW;
+    if (c->host_ctl->status & FZS_MISMATCH) return FZ_EINVAL;
+    FZ_TRY(hipMemcpy(out, c->rows_out.p, nranks * P.d_user * 4, hipMemcpyDeviceToHost));
+    return FZ_OK;
+}
+
+int fz_last_stats(fz_stats *out)
+{
+    if (out == nullptr) return FZ_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    int rc = get_ctx(&c);
+    if (rc) return rc;
+    *out = c->last;
+    return FZ_OK;
+}
+
+int fz_config_set(const char *key, int64_t value)
+{
+    if (key == nullptr || value < 0 || value > (1 << 20)) return FZ_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (std::strcmp(key, "slices_per_wave") == 0) g_slices_per_wave = (uint32_t)value;
+    else if (std::strcmp(key, "workgroups_per_cu") == 0) g_wg_per_cu = (uint32_t)value;
+    else return FZ_EINVAL;
+    return FZ_OK;
+}
+
+int fz_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof = on != 0;
+    return FZ_OK;
+}
+
+int fz_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof_stats.clear();
+    return FZ_OK;
+}
+
+int fz_profile_read(const char *kernel, double *total_ms, uint64_t *launches)
+{
+    if (kernel == nullptr || total_ms == nullptr || launches == nullptr) return FZ_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_prof_stats.find(kernel);
+    *total_ms = it == g_prof_stats.end() ? 0.0 : it->second.ms;
+    *launches = it == g_prof_stats.end() ? 0 : it->second.n;
+    return FZ_OK;
+}
+
+const char *fz_last_error(void)
+{
+    return g_err_msg;
+}
+
+const char *fz_strerror(int status)
+{
+    switch (status) {
+    case FZ_OK: return "ok";
+    case FZ_TRUNCATED: return "output truncated to max_tuples rows";
+    case FZ_EINVAL: return "invalid argument";
+    case FZ_EOVERFLOW: return "value out of range (n, generator or count too large)";
+    case FZ_ENOMEM: return "out of device memory";
+    case FZ_EDEVICE: return "HIP device error";
+    case FZ_E2BIG: return "last generator above FZ_MAX_LAST_GEN";
+    case FZ_EINTERNAL: return "internal self-check failed";
+    default: return "unknown status";
+    }
+}
+
+} // extern "C"

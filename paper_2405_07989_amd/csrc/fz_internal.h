@@ -1,0 +1,102 @@
+// fz_internal.h -- plan and buffer layout shared by the libfz host engine and
+// its HIP kernels.  Not part of the public ABI (include/fz.h is).
+//
+// Coordinates are 0-based here: the paper's a_1..a_d are a[0..d-1].  Calls
+// with d < 3 are padded in front with "virtual" coordinates whose generator
+// n+1 exceeds n, so they are always 0; every kernel therefore sees d >= 3 and
+// splits a tuple into
+//   a[0..M-1]      the row prefix (M = d-3), walked by a wave-uniform
+//                  odometer held in scalar registers,
+//   a[M]  = x      the lane coordinate: 64 consecutive values per chunk, one
+//                  per lane of the wavefront,
+//   a[d-2], a[d-1] the last pair, solved per lane: the valid a[d-2] for a
+//                  given remainder form an arithmetic progression with step
+//                  ord = g[d-1] / gcd(g[d-2], g[d-1]) (the modulo skip of
+//                  Sec. 3.2.4), so a lane steps through exactly the elements.
+#pragma once
+#include <stdint.h>
+
+#define FZK_MAX_D 16            // effective (padded) dimension bound
+#define FZK_SENTINEL 0xFFFFFFFFu
+#define FZK_NONE_E (1 << 30)    // residue-table mark: no solution in class
+#define FZK_WAVE 64
+#define FZK_WG 256              // threads per workgroup of the walker
+
+enum FzMode { FZM_COUNT = 0, FZM_HIST = 1, FZM_EXISTS = 2, FZM_STORE = 3 };
+
+// Division by an invariant 32-bit divisor (Granlund and Montgomery, "Division
+// by invariant integers using multiplication", PLDI 1994, Fig. 4.1):
+// t = mulhi(m, x); q = (t + ((x - t) >> s1)) >> s2.  Exact for every x < 2^32.
+struct FzFastDiv {
+    uint32_t m, s1, s2, d;
+};
+
+struct FzPlan {
+    uint32_t n;
+    uint32_t d;          // effective dimension, >= 3
+    uint32_t d_user;     // the caller's d
+    uint32_t pad;        // d - d_user virtual leading coordinates
+    uint32_t g[FZK_MAX_D];
+    uint32_t G2;         // g[d-3], generator of the lane coordinate
+    uint32_t A, B;       // g[d-2], g[d-1]
+    uint32_t D;          // gcd(A, B)
+    uint32_t ord;        // B / D: step of a[d-2] between elements
+    uint32_t delta;      // A / D: matching decrease of a[d-1]
+    uint32_t inv;        // (A/D)^{-1} mod ord
+    uint32_t mode;
+    FzFastDiv div_B, div_delta;
+    uint32_t nbins;      // histogram bins (n / min g + 1)
+    uint32_t hist_in_lds;
+    uint32_t n_slices;   // W
+    uint32_t stride;     // n + 1: row length of the count table
+    uint64_t target_len; // predicate target
+    uint64_t max_tuples; // store limit; UINT64_MAX for the other consumers
+};
+
+// Control block in device memory.  The slice cursor and the early-exit flag
+// sit on their own 128-byte lines.
+struct FzCtl {
+    uint32_t cursor;
+    uint32_t pad0[31];
+    uint32_t found;
+    uint32_t pad1[31];
+    uint32_t status;     // FZS_* bits
+    uint32_t pad2;
+    uint64_t total;      // |Z| from the count table
+    uint64_t count;      // elements the walkers visited
+    uint64_t rows, prefixes;
+    uint64_t min_len, max_len;
+    uint64_t written;
+};
+
+enum { FZS_OVERFLOW = 1u, FZS_MISMATCH = 2u };
+
+// Per-slice record written by the walker (one wave per slice).
+struct FzSliceRec {
+    uint64_t elements;
+    uint64_t rows;
+    uint64_t prefixes;
+};
+
+struct FzBufs {
+    uint64_t *S;          // count table: rows k = 0..d-2, each n+1 words
+    int2 *restab;         // B entries: {t0, E}
+    uint32_t *bounds;     // (W+1) x (d-2) slice start prefixes a[0..M]
+    uint64_t *base;       // (W+1) rank of the first element of each slice
+    FzSliceRec *recs;     // W
+    FzCtl *ctl;
+    uint64_t *hist_rows;  // nwg x nbins partial histograms
+    uint64_t *hist;       // nbins final histogram
+    uint32_t *out;        // store destination (row-major [.][d_user])
+};
+
+// Launchers (fz_kernels.hip).
+#include <hip/hip_runtime.h>
+hipError_t fzk_launch_dp(const FzPlan &p, const FzBufs &b, hipStream_t s);
+hipError_t fzk_launch_restab(const FzPlan &p, const FzBufs &b, hipStream_t s);
+hipError_t fzk_launch_slices(const FzPlan &p, const FzBufs &b, hipStream_t s);
+hipError_t fzk_launch_enum(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s);
+hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s);
+hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *ranks,
+                             uint64_t nranks, uint32_t *out, hipStream_t s);
+size_t fzk_enum_lds_bytes(const FzPlan &p);
