@@ -21,8 +21,9 @@
  * Conventions shared by every entry point
  *   n, g, d   the element, a HOST pointer to d generators (read during the
  *             call only, never retained), and the dimension.
- *   limits    1 <= d <= FZ_MAX_D; every g_i >= 1; n + max_i g_i < 2^31;
- *             n < 2^30 when d <= 2; g_d <= FZ_MAX_LAST_GEN.  Breaking one
+ *   limits    1 <= d <= FZ_MAX_D; every g_i >= 1; n + 2 max_i g_i < 2^31
+ *             (for d = 1 also n + 2 (n + 1) < 2^31); n < 2^30 when d <= 2;
+ *             g_d <= FZ_MAX_LAST_GEN.  Breaking one
  *             returns FZ_EINVAL (d, g, NULL pointers) or FZ_EOVERFLOW (sizes)
  *             or FZ_E2BIG (g_d), and no output is written.
  *   counts    exact unsigned 64-bit; a set with 2^64 - 1 or more elements
@@ -127,9 +128,25 @@ typedef struct {
 } fz_stats;
 int fz_last_stats(fz_stats *out);
 
+/* Per-slice record of the last successful enumeration on this device: the
+ * elements and rows of each slice and the device wall clock (100 MHz ticks)
+ * when a wavefront took it and finished it; for judging the balance of the
+ * slice cut.  Copies min(cap, slices) records, *n_slices = slices. */
+typedef struct {
+    uint64_t elements;
+    uint64_t rows;
+    uint64_t t_begin;
+    uint64_t t_end;
+} fz_slice_info;
+int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
+
 /* Tuning knobs (0 restores the default): "slices_per_wave" (slices cut per
  * resident wavefront), "workgroups_per_cu" (persistent workgroups per compute
- * unit).  FZ_EINVAL for an unknown key or a negative value. */
+ * unit), "work_row", "work_chunk", "work_element" (weights, in 1/64 of a
+ * wavefront instruction, of a row a_1..a_{d-3}, of a 64-lane chunk of a row
+ * and of an element, when slices are cut to equal work).  FZ_EINVAL for an
+ * unknown key or a value outside 0..2^20.  Results never depend on the
+ * knobs. */
 int fz_config_set(const char *key, int64_t value);
 
 /* Kernel timing with HIP events on the launch stream.  fz_profile_enable(1)

@@ -50,6 +50,11 @@ class fz_stats(ctypes.Structure):
                 ("elements", ctypes.c_uint64)]
 
 
+class fz_slice_info(ctypes.Structure):
+    _fields_ = [("elements", ctypes.c_uint64), ("rows", ctypes.c_uint64),
+                ("t_begin", ctypes.c_uint64), ("t_end", ctypes.c_uint64)]
+
+
 _u64, _u32, _i64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -65,6 +70,8 @@ _SIGS = {
     "fz_enumerate_device": (ctypes.c_int, [_u64, _u32p, _u32, _vp, _u64, _u64p, _u64p, _vp]),
     "fz_unrank": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _u64, _u32p]),
     "fz_last_stats": (ctypes.c_int, [ctypes.POINTER(fz_stats)]),
+    "fz_last_slices": (ctypes.c_int, [ctypes.POINTER(fz_slice_info), _u32,
+                                      ctypes.POINTER(ctypes.c_uint32)]),
     "fz_config_set": (ctypes.c_int, [ctypes.c_char_p, _i64]),
     "fz_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "fz_profile_reset": (ctypes.c_int, []),
@@ -175,6 +182,17 @@ def last_stats() -> dict:
     s = fz_stats()
     _check(_lib.fz_last_stats(ctypes.byref(s)), "fz_last_stats")
     return {k: getattr(s, k) for k, _ in fz_stats._fields_}
+
+
+def last_slices():
+    """Per-slice records of the last enumeration as a numpy structured array
+    (elements, rows, t_begin, t_end; clocks in 100 MHz ticks)."""
+    n = ctypes.c_uint32(0)
+    _check(_lib.fz_last_slices(None, 0, ctypes.byref(n)), "fz_last_slices")
+    buf = (fz_slice_info * max(n.value, 1))()
+    _check(_lib.fz_last_slices(buf, n.value, ctypes.byref(n)), "fz_last_slices")
+    arr = np.ctypeslib.as_array(buf)[: n.value]
+    return arr.copy()
 
 
 def config_set(key: str, value: int) -> None:

@@ -17,10 +17,21 @@
 namespace {
 
 constexpr int kMaxDevices = 64;
-constexpr uint32_t kDefaultSlicesPerWave = 4;
+constexpr uint32_t kDefaultSlicesPerWave = 16;
 constexpr uint32_t kDefaultWgPerCu = 8;
 constexpr uint32_t kMaxSlices = 1u << 22;
 constexpr size_t kLdsHistBudget = 64 * 1024;
+constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
+// Work model of the walker for cutting slices, in 1/64 of a wave instruction
+// (measured on the compiled walker): a row costs about 50 instructions (the
+// odometer step and the row bounds), a 64-lane chunk about 23 plus one trip
+// of the element loop (7 instructions, two candidate steps) per two units of
+// the spread of progression lengths across its lanes, and an element about
+// 3.5/64 (its share of a trip) when counted, more when binned or stored.
+constexpr double kWorkRow = 50.0 * 64;
+constexpr double kWorkChunk = 23.0 * 64;
+constexpr double kWorkTrip = 7.0 * 64;
+constexpr double kWorkElem[4] = {4, 8, 5, 40}; // count, hist, exists, store
 
 struct DevBuf {
     void *p = nullptr;
@@ -33,7 +44,7 @@ struct Ctx {
     int cus = 0;
     hipStream_t stream = nullptr;
     FzCtl *host_ctl = nullptr; // pinned
-    DevBuf S, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out, sentry;
+    DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out;
     fz_stats last{};
 };
 
@@ -41,6 +52,9 @@ std::mutex g_mu;
 Ctx g_ctx[kMaxDevices];
 uint32_t g_slices_per_wave = 0;
 uint32_t g_wg_per_cu = 0;
+uint32_t g_work_row = 0;
+uint32_t g_work_chunk = 0;
+uint32_t g_work_elem = 0;
 
 struct ProfEntry {
     double ms = 0;
@@ -183,7 +197,10 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
         maxg = std::max<uint64_t>(maxg, g[i]);
         ming = std::min<uint64_t>(ming, g[i]);
     }
-    if (n + maxg >= (1ull << 31)) return FZ_EOVERFLOW;
+    // every coordinate, remainder and walker counter stays a non-negative
+    // int32; the virtual generator of d = 1 is n + 1
+    const uint64_t maxa = d == 1 ? std::max<uint64_t>(maxg, n + 1) : maxg;
+    if (n + 2 * maxa >= (1ull << 31)) return FZ_EOVERFLOW;
     if (d <= 2 && n >= (1ull << 30)) return FZ_EOVERFLOW;
     if (g[d - 1] > FZ_MAX_LAST_GEN) return FZ_E2BIG;
     std::memset(P, 0, sizeof *P);
@@ -204,6 +221,15 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
     P->mode = mode;
     P->div_B = make_fastdiv(P->B);
     P->div_delta = make_fastdiv(P->delta);
+    P->div_G2 = make_fastdiv(P->G2);
+    // lanes of a chunk differ by up to 63 G2 in remainder, i.e. by about
+    // 63 G2 D / (A B) elements in progression length
+    const double spread = 63.0 * P->G2 * P->D / ((double)P->A * P->B);
+    const double wchunk = kWorkChunk + kWorkTrip * (std::min(spread, 1e4) / 2 + 1);
+    P->w_row = g_work_row ? g_work_row : (uint32_t)kWorkRow;
+    P->w_chunk = g_work_chunk ? g_work_chunk : (uint32_t)(wchunk + 0.5);
+    P->w_el = g_work_elem ? g_work_elem : (uint32_t)kWorkElem[mode & 3];
+    P->restab_in_lds = (size_t)2 * P->B * sizeof(int2) <= kLdsRestabBudget;
     P->nbins = (uint32_t)(n / ming + 1);
     P->stride = (uint32_t)n + 1;
     P->target_len = 0;
@@ -259,11 +285,13 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     P.n_slices = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(waves * spw, 1), kMaxSlices);
     L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
-    P.hist_in_lds =
-        (P.mode == FZM_HIST) && ((size_t)(FZK_WG / FZK_WAVE) * P.nbins * 4 <= kLdsHistBudget);
+    P.hist_in_lds = (P.mode == FZM_HIST) &&
+                    ((size_t)(FZK_WG / FZK_WAVE) * (P.nbins + FZK_WAVE) * 4 <= kLdsHistBudget);
     const uint64_t table_words = (uint64_t)(P.d - 1) * P.stride;
+    const uint64_t cost_words = (uint64_t)(P.d - 2) * P.stride;
     FZ_TRY(ensure(c.S, table_words * 8));
-    FZ_TRY(ensure(c.restab, (size_t)P.B * sizeof(int2)));
+    FZ_TRY(ensure(c.C, cost_words * 8));
+    FZ_TRY(ensure(c.restab, (size_t)2 * P.B * sizeof(int2)));
     FZ_TRY(ensure(c.bounds, (size_t)(P.n_slices + 1) * (P.d - 2) * 4));
     FZ_TRY(ensure(c.base, (size_t)(P.n_slices + 1) * 8));
     FZ_TRY(ensure(c.recs, (size_t)P.n_slices * sizeof(FzSliceRec)));
@@ -273,6 +301,7 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
         if (P.hist_in_lds) FZ_TRY(ensure(c.hist_rows, (size_t)L.nwg * P.nbins * 8));
     }
     B.S = (uint64_t *)c.S.p;
+    B.C = (uint64_t *)c.C.p;
     B.restab = (int2 *)c.restab.p;
     B.bounds = (uint32_t *)c.bounds.p;
     B.base = (uint64_t *)c.base.p;
@@ -498,12 +527,37 @@ int fz_last_stats(fz_stats *out)
     return FZ_OK;
 }
 
+int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices)
+{
+    if (n_slices == nullptr || (out == nullptr && cap > 0)) return FZ_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *c;
+    int rc = get_ctx(&c);
+    if (rc) return rc;
+    const uint32_t n = (uint32_t)c->last.slices;
+    *n_slices = n;
+    const uint32_t k = std::min(n, cap);
+    if (k == 0) return FZ_OK;
+    std::vector<FzSliceRec> tmp(k);
+    FZ_TRY(hipMemcpy(tmp.data(), c->recs.p, k * sizeof(FzSliceRec), hipMemcpyDeviceToHost));
+    for (uint32_t i = 0; i < k; ++i) {
+        out[i].elements = tmp[i].elements;
+        out[i].rows = tmp[i].rows;
+        out[i].t_begin = tmp[i].t_begin;
+        out[i].t_end = tmp[i].t_end;
+    }
+    return FZ_OK;
+}
+
 int fz_config_set(const char *key, int64_t value)
 {
     if (key == nullptr || value < 0 || value > (1 << 20)) return FZ_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     if (std::strcmp(key, "slices_per_wave") == 0) g_slices_per_wave = (uint32_t)value;
     else if (std::strcmp(key, "workgroups_per_cu") == 0) g_wg_per_cu = (uint32_t)value;
+    else if (std::strcmp(key, "work_row") == 0) g_work_row = (uint32_t)value;
+    else if (std::strcmp(key, "work_chunk") == 0) g_work_chunk = (uint32_t)value;
+    else if (std::strcmp(key, "work_element") == 0) g_work_elem = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

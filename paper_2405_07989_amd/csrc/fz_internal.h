@@ -44,7 +44,11 @@ struct FzPlan {
     uint32_t delta;      // A / D: matching decrease of a[d-1]
     uint32_t inv;        // (A/D)^{-1} mod ord
     uint32_t mode;
-    FzFastDiv div_B, div_delta;
+    FzFastDiv div_B, div_delta, div_G2;
+    uint32_t w_row;      // slice-cut weight of one row (prefix a[0..M-1])
+    uint32_t w_chunk;    // ... of one 64-lane chunk of a row
+    uint32_t w_el;       // ... of one element
+    uint32_t restab_in_lds;
     uint32_t nbins;      // histogram bins (n / min g + 1)
     uint32_t hist_in_lds;
     uint32_t n_slices;   // W
@@ -75,12 +79,15 @@ enum { FZS_OVERFLOW = 1u, FZS_MISMATCH = 2u };
 struct FzSliceRec {
     uint64_t elements;
     uint64_t rows;
-    uint64_t prefixes;
+    uint64_t prefixes;   // lane prefixes a[0..M] visited
+    uint64_t t_begin;    // device wall clock (100 MHz) when the wave took it
+    uint64_t t_end;
 };
 
 struct FzBufs {
     uint64_t *S;          // count table: rows k = 0..d-2, each n+1 words
-    int2 *restab;         // B entries: {t0, E}
+    uint64_t *C;          // work table: rows k = 0..M, each n+1 words
+    int2 *restab;         // 2B entries {t0, E2}, indexed by rho' = rho + B - lr
     uint32_t *bounds;     // (W+1) x (d-2) slice start prefixes a[0..M]
     uint64_t *base;       // (W+1) rank of the first element of each slice
     FzSliceRec *recs;     // W

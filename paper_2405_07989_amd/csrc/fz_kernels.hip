@@ -29,17 +29,17 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FzFastDiv &f)
     return (t + ((x - t) >> f.s1)) >> f.s2;
 }
 
-__device__ __forceinline__ uint32_t uni(uint32_t x)
-{
-    return __builtin_amdgcn_readfirstlane(x);
-}
-
 // A lane's 64-bit value read by the whole wave (a wave-uniform result).
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
 {
     const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
     const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
     return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x)
+{
+    return __builtin_amdgcn_readfirstlane(x);
 }
 
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane)
@@ -60,6 +60,15 @@ __device__ __forceinline__ uint64_t wave_incl_scan64(uint64_t v, uint32_t lane)
         if (lane >= (uint32_t)o) v += t;
     }
     return v;
+}
+
+// Sum of a per-lane 64-bit value over the wave, returned to every lane as a
+// wave-uniform value.
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v)
+{
+#pragma unroll
+    for (int o = FZK_WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, FZK_WAVE);
+    return readlane64(v, 0);
 }
 
 // S[d-1][v] = [g[d-1] divides v]; rows 0..d-2 are stored.
@@ -90,61 +99,115 @@ __device__ __forceinline__ uint32_t unrank_level(const uint64_t *Srow, uint32_t 
 } // namespace
 
 // ---------------------------------------------------------------------------
-// Count table.  S[k][v] = #{(a_k..a_{d-1}) >= 0 : sum_{j>=k} a_j g_j = v}
-// satisfies S[k][v] = S[k+1][v] + S[k][v - g_k]: along each chain
-// v = c, c + g_k, c + 2 g_k, ... row k is the running sum of row k+1.  One
-// workgroup builds all rows; a row is g_k independent chains, each cut into
-// row blocks (partial sums, a carry scan, then the final pass).  Saturating
-// adds: |Z| = S[0][n] = 2^64-1 flags overflow.
+// Count and work tables.  S[k][v] = #{(a_k..a_{d-1}) >= 0 : sum_{j>=k} a_j g_j
+// = v} satisfies S[k][v] = S[k+1][v] + S[k][v - g_k]: along each chain
+// v = c, c + g_k, c + 2 g_k, ... row k is the running sum of row k+1.  The
+// work table C models what a wave pays: C[M][v] is the work of one row with
+// remainder v (row_work), and C[k][v] = C[k+1][v] + C[k][v - g_k] sums it
+// over the subtrees, so slices can be cut to equal work.
+// One workgroup builds all rows; a row is g_k independent chains, each cut
+// into row blocks (partial sums, a carry scan, then the final pass).
+// Saturating adds: S[0][n] = 2^64-1 flags overflow.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
+// Work of the first t lanes (x = 0..t-1) of a row with remainder v: the row
+// itself, its 64-lane chunks and its elements.  t = floor(v / G2) + 1 is the
+// whole row.  Non-decreasing in t.
+__device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM, uint32_t v,
+                                             uint32_t t)
 {
-    __shared__ uint64_t part[1024];
+    if (t == 0) return 0;
+    const uint64_t el = SM[v] - (t * (uint64_t)P.G2 <= v ? SM[v - t * P.G2] : 0);
+    const uint64_t chunks = (t + FZK_WAVE - 1) / FZK_WAVE;
+    uint64_t w = P.w_row + chunks * P.w_chunk;
+    const uint64_t we = el * P.w_el;
+    return (P.w_el && we / P.w_el != el) ? ~0ull : sat_add(w, we);
+}
+
+template <class Below>
+__device__ void chain_scan(const FzPlan &P, uint64_t *row, uint32_t gk, Below below,
+                           uint64_t *part)
+{
     const uint32_t T = blockDim.x, tid = threadIdx.x;
-    uint64_t *S = Bf.S;
-    for (int k = (int)P.d - 2; k >= 0; --k) {
-        const uint32_t gk = P.g[k];
-        uint64_t *row = S + (uint64_t)k * P.stride;
-        const uint32_t rows = P.n / gk + 1;
-        const uint32_t cols = gk < P.stride ? gk : P.stride;
-        const uint32_t nb = cols >= T ? 1 : T / cols;
-        const uint32_t rpb = (rows + nb - 1) / nb;
-        const uint32_t units = cols * nb;
-        if (nb > 1) {
-            for (uint32_t u = tid; u < units; u += T) {
-                const uint32_t c = u % cols, b = u / cols;
-                const uint32_t i1 = min(rows, (b + 1) * rpb);
-                uint64_t s = 0;
-                for (uint32_t i = b * rpb; i < i1; ++i) {
-                    const uint64_t v = (uint64_t)i * gk + c;
-                    if (v > P.n) break;
-                    s = sat_add(s, table_below(P, S, k, (uint32_t)v));
-                }
-                part[u] = s;
-            }
-            __syncthreads();
-            for (uint32_t c = tid; c < cols; c += T) {
-                uint64_t carry = 0;
-                for (uint32_t b = 0; b < nb; ++b) {
-                    const uint64_t t = part[b * cols + c];
-                    part[b * cols + c] = carry;
-                    carry = sat_add(carry, t);
-                }
-            }
-            __syncthreads();
-        }
+    const uint32_t rows = P.n / gk + 1;
+    const uint32_t cols = gk < P.stride ? gk : P.stride;
+    const uint32_t nb = cols >= T ? 1 : T / cols;
+    const uint32_t rpb = (rows + nb - 1) / nb;
+    const uint32_t units = cols * nb;
+    if (nb > 1) {
         for (uint32_t u = tid; u < units; u += T) {
             const uint32_t c = u % cols, b = u / cols;
             const uint32_t i1 = min(rows, (b + 1) * rpb);
-            uint64_t run = nb > 1 ? part[u] : 0;
-            for (uint32_t i = b * rpb; i < i1; ++i) {
-                const uint64_t v = (uint64_t)i * gk + c;
-                if (v > P.n) break;
-                run = sat_add(run, table_below(P, S, k, (uint32_t)v));
-                row[v] = run;
+            uint64_t s = 0;
+            // independent loads first, then the dependent sum
+            for (uint32_t i = b * rpb; i < i1; i += 8) {
+                uint64_t x[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint64_t v = (uint64_t)(i + q) * gk + c;
+                    x[q] = (i + q < i1 && v <= P.n) ? below((uint32_t)v) : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) s = sat_add(s, x[q]);
+            }
+            part[u] = s;
+        }
+        __syncthreads();
+        for (uint32_t c = tid; c < cols; c += T) {
+            uint64_t carry = 0;
+            for (uint32_t b = 0; b < nb; ++b) {
+                const uint64_t t = part[b * cols + c];
+                part[b * cols + c] = carry;
+                carry = sat_add(carry, t);
             }
         }
         __syncthreads();
+    }
+    for (uint32_t u = tid; u < units; u += T) {
+        const uint32_t c = u % cols, b = u / cols;
+        const uint32_t i1 = min(rows, (b + 1) * rpb);
+        uint64_t run = nb > 1 ? part[u] : 0;
+        for (uint32_t i = b * rpb; i < i1; i += 8) {
+            uint64_t x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t v = (uint64_t)(i + q) * gk + c;
+                x[q] = (i + q < i1 && v <= P.n) ? below((uint32_t)v) : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t v = (uint64_t)(i + q) * gk + c;
+                run = sat_add(run, x[q]);
+                if (i + q < i1 && v <= P.n) row[v] = run;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
+{
+    __shared__ uint64_t part[1024];
+    uint64_t *S = Bf.S;
+    for (int k = (int)P.d - 2; k >= 0; --k) {
+        uint64_t *row = S + (uint64_t)k * P.stride;
+        const uint64_t *nxt = S + (uint64_t)(k + 1) * P.stride;
+        if (k + 1 == (int)P.d - 1)
+            chain_scan(P, row, P.g[k],
+                       [&](uint32_t v) { return (v - fdiv(v, P.div_B) * P.B) == 0 ? 1ull : 0ull; },
+                       part);
+        else
+            chain_scan(P, row, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
+    }
+    const int M = (int)P.d - 3;
+    uint64_t *CM = Bf.C + (uint64_t)M * P.stride;
+    const uint64_t *SM = S + (uint64_t)M * P.stride;
+    for (uint32_t v = threadIdx.x; v <= P.n; v += blockDim.x)
+        CM[v] = row_work(P, SM, v, fdiv(v, P.div_G2) + 1);
+    __syncthreads();
+    for (int k = M - 1; k >= 0; --k) {
+        uint64_t *row = Bf.C + (uint64_t)k * P.stride;
+        const uint64_t *nxt = Bf.C + (uint64_t)(k + 1) * P.stride;
+        chain_scan(P, row, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
     }
 }
 
@@ -153,12 +216,15 @@ __global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
 // rem = q B + rho the valid a[d-2] are t = t0 + j ord (j >= 0) with
 // A t0 == rho (mod B), 0 <= t0 < ord; then a[d-1] = q - E - j delta with
 // E = (A t0 - rho) / B.  Classes with gcd(A,B) not dividing rho have no
-// element: E = FZK_NONE_E makes a[d-1] negative.
+// element: E = FZK_NONE_E makes a[d-1] negative.  The table is doubled so
+// that a lane can index it with rho' = rho + B in [0, 2B) and quotient
+// q' = q - 1 without a borrow: entry rho' >= B holds E(rho' - B) - 1.
 // ---------------------------------------------------------------------------
 __global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
 {
-    const uint32_t rho = blockIdx.x * blockDim.x + threadIdx.x;
-    if (rho >= P.B) return;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * P.B) return;
+    const uint32_t rho = i < P.B ? i : i - P.B;
     int2 e;
     if (rho % P.D != 0) {
         e.x = 0;
@@ -168,24 +234,29 @@ __global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
         const uint64_t num = (uint64_t)P.A * t0 - rho;
         e.x = (int)t0;
         e.y = (int)(num / P.B);
+        if (i >= P.B) e.y -= 1;
     }
-    Bf.restab[rho] = e;
+    Bf.restab[i] = e;
 }
 
 // ---------------------------------------------------------------------------
-// Slice bounds.  Boundary j (0 <= j < W) is the prefix a[0..M] of the element
-// of rank floor(j N' / W), N' = min(|Z|, max_tuples); slice j walks prefixes
-// [bound j, bound j+1) and its first element has rank base[j] (the rank of the
-// first element with that prefix).  Boundary W is open (sentinel).  Thread 0
-// also resets the control block for the walker.
+// Slice bounds, cut by work.  Lane prefixes a[0..M] in lex order carry the
+// work of the wave that walks them (row_work).  Boundary j (0 <= j < W) is
+// the prefix at work rank floor(j Wtot / W): found level by level in the work
+// table for the row prefix a[0..M-1], then inside the row on the row_work of
+// its first t lanes.  Wtot covers the prefixes up to the one that holds
+// element rank N' - 1, N' = min(|Z|, max_tuples).  Slice j walks prefixes
+// [bound j, bound j+1); base[j] is the element rank of its first element.
+// Boundary W is open (sentinel).  Thread 0 also resets the control block.
 // ---------------------------------------------------------------------------
 __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t W = P.n_slices;
     const uint32_t np = P.d - 2;
+    const uint32_t M = P.d - 3;
     const uint64_t N = Bf.S[P.n];
-    const bool ovf = (N == ~0ull);
+    const bool ovf = (N == ~0ull) || (Bf.C[P.n] == ~0ull);
     if (j == 0) {
         FzCtl *c = Bf.ctl;
         c->cursor = 0;
@@ -200,25 +271,49 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
     if (j > W) return;
     const uint64_t Np = ovf ? 0 : (N < P.max_tuples ? N : P.max_tuples);
     uint32_t *out = Bf.bounds + (uint64_t)j * np;
-    if (j == W) {
-        Bf.base[W] = Np;
-        out[0] = FZK_SENTINEL;
-        return;
-    }
-    const uint64_t rank = (Np / W) * j + ((Np % W) * j) / W;
-    if (rank >= Np) {
+    if (j == W || Np == 0) {
         Bf.base[j] = Np;
         out[0] = FZK_SENTINEL;
         return;
     }
-    uint64_t r = rank;
+    const uint64_t *SM = Bf.S + (uint64_t)M * P.stride;
+    uint64_t Wtot;
+    if (Np == N) {
+        Wtot = Bf.C[P.n];
+    } else {
+        // work of the rows before the one that holds element rank Np-1, plus
+        // that row up to and including the lane holding it
+        uint64_t r = Np - 1, acc = 0;
+        uint32_t v = P.n;
+        for (uint32_t k = 0; k < M; ++k) {
+            const uint64_t *Ck = Bf.C + (uint64_t)k * P.stride;
+            const uint32_t t = unrank_level(Bf.S + (uint64_t)k * P.stride, v, P.g[k], r);
+            acc += Ck[v] - Ck[v - t * P.g[k]];
+            v -= t * P.g[k];
+        }
+        const uint32_t x = unrank_level(SM, v, P.G2, r);
+        Wtot = acc + row_work(P, SM, v, x + 1);
+    }
+    uint64_t rc = (Wtot / W) * j + ((Wtot % W) * j) / W;
+    uint64_t base = 0;
     uint32_t v = P.n;
-    for (uint32_t k = 0; k < np; ++k) {
-        const uint32_t t = unrank_level(Bf.S + (uint64_t)k * P.stride, v, P.g[k], r);
+    for (uint32_t k = 0; k < M; ++k) {
+        const uint64_t *Sk = Bf.S + (uint64_t)k * P.stride;
+        const uint32_t t = unrank_level(Bf.C + (uint64_t)k * P.stride, v, P.g[k], rc);
+        base += Sk[v] - Sk[v - t * P.g[k]];
         out[k] = t;
         v -= t * P.g[k];
     }
-    Bf.base[j] = rank - r;
+    // inside the row: largest t in [0, v / G2] whose first t lanes fit in rc
+    uint32_t lo = 0, hi = v / P.G2;
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (row_work(P, SM, v, mid) <= rc) lo = mid;
+        else hi = mid - 1;
+    }
+    out[M] = lo;
+    base += SM[v] - SM[v - lo * P.G2];
+    Bf.base[j] = base;
 }
 
 // ---------------------------------------------------------------------------
@@ -230,35 +325,52 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
 // progression of elements one candidate at a time (the modulo skip of
 // Sec. 3.2.4: a[d-2] += ord, a[d-1] -= delta), the step ending at the first
 // candidate with a[d-1] < 0.  The consumer sees every element.
+//
+// LDS: [residue table, 2B int2, when it fits][per-wave consumer scratch].
 // ---------------------------------------------------------------------------
-template <int M, int MODE>
+template <int M, int MODE, bool TLDS>
 __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
 {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __align__(16) uint32_t lds[];
     constexpr uint32_t NP = M + 1;
     const uint32_t lane = __lane_id();
     const uint32_t wave = threadIdx.x / FZK_WAVE;
     const uint32_t W = P.n_slices;
 
+    // TLDS: the residue table is staged in LDS (read with ds_read); else it
+    // is read from global memory.  Two instantiations keep each pointer's
+    // address space known to the compiler.
+    int2 *ltab = (int2 *)lds;
+    uint32_t *scratch = lds;
+    if constexpr (TLDS) {
+        for (uint32_t i = threadIdx.x; i < 2 * P.B; i += blockDim.x) ltab[i] = Bf.restab[i];
+        scratch = lds + 2 * (((2 * P.B) + 1) & ~1u); // keep 16-byte alignment
+    }
     uint32_t *wbins = nullptr;
     uint64_t *grow = nullptr;
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) {
-            wbins = lds + wave * P.nbins;
-            for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) wbins[i] = 0;
+            wbins = scratch + wave * (P.nbins + FZK_WAVE);
+            for (uint32_t i = lane; i < P.nbins + FZK_WAVE; i += FZK_WAVE) wbins[i] = 0;
             grow = Bf.hist_rows + (uint64_t)blockIdx.x * P.nbins;
             for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = 0;
         }
-        __syncthreads();
     }
-    uint64_t *s_incl = (uint64_t *)(lds + wave * (4 * FZK_WAVE));
+    // store scratch per wave: scan (64 x u64), t0 and ad0 (64 x u32 each),
+    // then the staging block of 64 rows x d_user words
+    const uint32_t store_words = 4 * FZK_WAVE + FZK_WAVE * P.d_user;
+    uint64_t *s_incl = (uint64_t *)(scratch + wave * store_words);
     uint32_t *s_t0 = (uint32_t *)(s_incl + FZK_WAVE);
     uint32_t *s_ad0 = s_t0 + FZK_WAVE;
+    uint32_t *s_stage = s_ad0 + FZK_WAVE;
+    __syncthreads();
 
-    // lane * G2 = lq * B + lr (exact whenever the lane is active)
+    // lane * G2 = lq * B + lr (exact whenever the lane is active).  A lane
+    // reads the doubled residue table at rho' = Pc + (B - lr) with quotient
+    // q' = Qc - (lq + 1): no borrow to propagate.
     const uint64_t lg = (uint64_t)lane * P.G2;
-    const uint32_t lq = (uint32_t)(lg / P.B);
-    const uint32_t lr = (uint32_t)(lg % P.B);
+    const uint32_t lq1 = (uint32_t)(lg / P.B) + 1;
+    const uint32_t lr2 = P.B - (uint32_t)(lg % P.B);
     const uint32_t len_step = P.ord - P.delta;
     const int32_t delta = (int32_t)P.delta;
     uint64_t hist_since_flush = 0;
@@ -275,9 +387,14 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
                 __hip_atomic_load(&Bf.ctl->found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if (uni(f)) break;
         }
+        const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
         const uint32_t *b1 = b0 + NP;
-        uint64_t n_el = 0, n_rows = 0, n_pref = 0;
+        // per-lane element counters: a chunk adds at most n + 1 per lane to
+        // the 32-bit counter, which is folded into the 64-bit one per chunk
+        uint64_t lane_el = 0;
+        uint32_t lane_pref = 0;
+        uint64_t n_el = 0, n_rows = 0;
         if (uni(b0[0]) != FZK_SENTINEL) {
             uint32_t a[M > 0 ? M : 1];
             uint32_t e[M > 0 ? M : 1];
@@ -288,15 +405,15 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
                 a[k] = uni(b0[k]);
                 rr[k + 1] = rr[k] - a[k] * P.g[k];
             }
-            uint32_t xs = uni(b0[M]);
+            int32_t xs = (int32_t)uni(b0[M]);
             const bool end_open = uni(b1[0]) == FZK_SENTINEL;
-            uint32_t xe = 0;
+            int32_t xe = 0;
 #pragma unroll
             for (int k = 0; k < M; ++k) e[k] = 0;
             if (!end_open) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) e[k] = uni(b1[k]);
-                xe = uni(b1[M]);
+                xe = (int32_t)uni(b1[M]);
             }
             uint32_t plen = 0;
 #pragma unroll
@@ -305,73 +422,80 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
             bool done = false;
             while (!done) {
                 const uint32_t Rp = rr[M];
-                const uint32_t xhi = Rp / P.G2;
+                const int32_t xhi = (int32_t)fdiv(Rp, P.div_G2);
                 bool last = !end_open;
 #pragma unroll
                 for (int k = 0; k < M; ++k) last = last && (a[k] == e[k]);
-                const int64_t xlast = last ? (int64_t)xe - 1 : (int64_t)xhi;
+                const int32_t xlast = last ? xe - 1 : xhi;
                 ++n_rows;
                 if constexpr (MODE == FZM_EXISTS) {
                     const uint32_t f = __hip_atomic_load(&Bf.ctl->found, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                     if (uni(f)) break;
                 }
-                for (int64_t c = xs; c <= xlast; c += FZK_WAVE) {
+                for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
                     const uint32_t Rc = Rp - (uint32_t)c * P.G2;
                     const uint32_t Qc = fdiv(Rc, P.div_B);
                     const uint32_t Pc = Rc - Qc * P.B;
-                    const bool active = (int64_t)lane <= xlast - c;
-                    uint32_t rho = Pc - lr;
-                    uint32_t qv = Qc - lq;
-                    if ((int32_t)rho < 0) {
-                        rho += P.B;
-                        qv -= 1;
-                    }
-                    int2 ent = make_int2(0, FZK_NONE_E);
-                    if (active) ent = Bf.restab[rho];
+                    const bool active = (int32_t)lane <= xlast - c;
+                    const uint32_t rho2 = Pc + lr2;
+                    const int32_t q2 = (int32_t)(Qc - lq1);
+                    const uint32_t ti = active ? rho2 : 0u;
+                    const int2 ent = TLDS ? ltab[ti] : Bf.restab[ti];
                     // a lane with no element starts at -1, so that the common
-                    // decrement stays above -(n + A) > -2^31 for every lane
-                    int32_t ad0 = active ? (int32_t)qv - ent.y : -1;
-                    ad0 = ad0 < 0 ? -1 : ad0;
-                    n_pref += __popcll(__ballot(active));
+                    // decrement stays above -(n + 2 A) > -2^31 for every lane
+                    int32_t ad0 = q2 - ent.y;
+                    ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                    lane_pref += active ? 1u : 0u;
+                    uint32_t cnt = 0;
                     if constexpr (MODE == FZM_COUNT) {
+                        // two candidate steps per trip; the trip test is the
+                        // first step's own validity test
                         int32_t ad = ad0;
                         for (;;) {
-                            const uint64_t m = __ballot(ad >= 0);
-                            if (!m) break;
-                            n_el += __popcll(m);
-                            ad -= delta;
+                            const bool c0 = ad >= 0;
+                            if (!__ballot(c0)) break;
+                            const bool c1 = ad >= delta;
+                            cnt += c0 ? 1u : 0u;
+                            cnt += c1 ? 1u : 0u;
+                            ad -= 2 * delta;
                         }
+                        lane_el += cnt;
                     } else if constexpr (MODE == FZM_HIST) {
                         int32_t ad = ad0;
                         uint32_t len = plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
                         uint64_t *gh = Bf.hist;
+                        // lanes without an element add into a private spare bin
+                        const uint32_t spare = P.nbins + lane;
                         for (;;) {
-                            const uint64_t m = __ballot(ad >= 0);
-                            if (!m) break;
-                            n_el += __popcll(m);
-                            if (ad >= 0) {
-                                if (P.hist_in_lds) atomicAdd(&wbins[len], 1u);
-                                else atomicAdd((unsigned long long *)&gh[len], 1ull);
+                            const bool c0 = ad >= 0;
+                            if (!__ballot(c0)) break;
+                            cnt += c0 ? 1u : 0u;
+                            if (P.hist_in_lds) {
+                                atomicAdd(&wbins[c0 ? len : spare], 1u);
+                            } else if (c0) {
+                                atomicAdd((unsigned long long *)&gh[len], 1ull);
                             }
                             ad -= delta;
                             len += len_step;
                         }
+                        lane_el += cnt;
                     } else if constexpr (MODE == FZM_EXISTS) {
                         int32_t ad = ad0;
                         uint32_t len = plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
                         bool hit = false;
                         for (;;) {
-                            const uint64_t m = __ballot(ad >= 0);
-                            if (!m) break;
-                            n_el += __popcll(m);
-                            if (__ballot(ad >= 0 && (uint64_t)len == P.target_len)) {
+                            const bool c0 = ad >= 0;
+                            if (!__ballot(c0)) break;
+                            cnt += c0 ? 1u : 0u;
+                            if (__ballot(c0 && (uint64_t)len == P.target_len)) {
                                 hit = true;
                                 break;
                             }
                             ad -= delta;
                             len += len_step;
                         }
+                        lane_el += cnt;
                         if (hit) {
                             __hip_atomic_store(&Bf.ctl->found, 1u, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
@@ -389,11 +513,17 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         __builtin_amdgcn_wave_barrier();
                         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        // Rows are produced 64 at a time (lane = position in
+                        // the chunk's output), staged in LDS as one
+                        // contiguous block and written out as consecutive
+                        // dwords: every store instruction covers 256 bytes.
                         const uint64_t lim = P.max_tuples;
+                        const uint32_t du = P.d_user;
                         for (uint64_t p0 = 0; p0 < T && rank + p0 < lim; p0 += FZK_WAVE) {
+                            const uint64_t left = T - p0 < lim - rank - p0 ? T - p0 : lim - rank - p0;
+                            const uint32_t nb = left < FZK_WAVE ? (uint32_t)left : FZK_WAVE;
                             const uint64_t p = p0 + lane;
-                            const uint64_t row = rank + p;
-                            if (p < T && row < lim) {
+                            if (lane < nb) {
                                 uint32_t j = 0;
 #pragma unroll
                                 for (uint32_t st = FZK_WAVE / 2; st >= 1; st >>= 1)
@@ -405,11 +535,20 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
                                 v[M] = (uint32_t)c + j;
                                 v[M + 1] = s_t0[j] + k * P.ord;
                                 v[M + 2] = s_ad0[j] - k * P.delta;
-                                uint32_t *dst = Bf.out + row * P.d_user - P.pad;
+                                uint32_t *st_row = s_stage + lane * du - P.pad;
 #pragma unroll
                                 for (int q = 0; q < M + 3; ++q)
-                                    if ((uint32_t)q >= P.pad) dst[q] = v[q];
+                                    if ((uint32_t)q >= P.pad) st_row[q] = v[q];
                             }
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                            uint32_t *dst = Bf.out + (rank + p0) * du;
+                            const uint32_t words = nb * du;
+                            for (uint32_t i = lane; i < words; i += FZK_WAVE) dst[i] = s_stage[i];
+                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                            __builtin_amdgcn_wave_barrier();
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                         }
                         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                         __builtin_amdgcn_wave_barrier();
@@ -445,11 +584,14 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
                 xs = 0;
             }
         }
+        if constexpr (MODE != FZM_STORE) n_el = wave_sum64(lane_el);
         {
             FzSliceRec rec;
             rec.elements = n_el;
             rec.rows = n_rows;
-            rec.prefixes = n_pref;
+            rec.prefixes = wave_sum64(lane_pref);
+            rec.t_begin = t_begin;
+            rec.t_end = wall_clock64();
             Bf.recs[s] = rec; // the same value from every lane
         }
         if constexpr (MODE == FZM_HIST) {
@@ -594,7 +736,7 @@ hipError_t fzk_launch_dp(const FzPlan &p, const FzBufs &b, hipStream_t s)
 
 hipError_t fzk_launch_restab(const FzPlan &p, const FzBufs &b, hipStream_t s)
 {
-    const uint32_t blocks = (p.B + 255) / 256;
+    const uint32_t blocks = (2 * p.B + 255) / 256;
     hipLaunchKernelGGL(fz_restab_kernel, dim3(blocks), dim3(256), 0, s, p, b);
     return hipGetLastError();
 }
@@ -611,29 +753,43 @@ hipError_t fzk_launch_slices(const FzPlan &p, const FzBufs &b, hipStream_t s)
 size_t fzk_enum_lds_bytes(const FzPlan &p)
 {
     const uint32_t waves = FZK_WG / FZK_WAVE;
-    if (p.mode == FZM_HIST && p.hist_in_lds) return (size_t)waves * p.nbins * sizeof(uint32_t);
-    if (p.mode == FZM_STORE) return (size_t)waves * 4 * FZK_WAVE * sizeof(uint32_t);
-    return 0;
+    size_t bytes = p.restab_in_lds ? (size_t)2 * ((2 * p.B + 1) & ~1u) * sizeof(uint32_t) : 0;
+    if (p.mode == FZM_HIST && p.hist_in_lds)
+        bytes += (size_t)waves * (p.nbins + FZK_WAVE) * sizeof(uint32_t);
+    if (p.mode == FZM_STORE)
+        bytes += (size_t)waves * (4 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
+    return bytes;
+}
+
+template <int M, bool TLDS>
+static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
+{
+    const size_t lds = fzk_enum_lds_bytes(p);
+    switch (p.mode) {
+    case FZM_COUNT:
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_COUNT, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
+                           p, b);
+        break;
+    case FZM_HIST:
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
+                           p, b);
+        break;
+    case FZM_EXISTS:
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
+                           p, b);
+        break;
+    default:
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
+                           p, b);
+        break;
+    }
 }
 
 template <int M>
 static hipError_t launch_enum_m(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
-    const size_t lds = fzk_enum_lds_bytes(p);
-    switch (p.mode) {
-    case FZM_COUNT:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_COUNT>), dim3(nwg), dim3(FZK_WG), lds, s, p, b);
-        break;
-    case FZM_HIST:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST>), dim3(nwg), dim3(FZK_WG), lds, s, p, b);
-        break;
-    case FZM_EXISTS:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS>), dim3(nwg), dim3(FZK_WG), lds, s, p, b);
-        break;
-    default:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE>), dim3(nwg), dim3(FZK_WG), lds, s, p, b);
-        break;
-    }
+    if (p.restab_in_lds) launch_enum_mt<M, true>(p, b, nwg, s);
+    else launch_enum_mt<M, false>(p, b, nwg, s);
     return hipGetLastError();
 }
 
