@@ -33,8 +33,36 @@ OPS_PER_ELEMENT = 3
 OPS_PER_PREFIX = 8
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_enum_d6_n100000.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2405_07989_amd", "csrc", "fz_kernels.hip")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of each walker from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size);
+    None when the file is missing or the walker source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            line = line.strip()
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return {k: float(v) for k, v in vals.items() if k.endswith("_bytes")}
 
 
 def cpu_baseline(n, g, seconds_target=15.0):
@@ -69,6 +97,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy 1 GiB device to device 3 times (the "
+                         "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -169,6 +200,19 @@ def main():
     }
     del out
     torch.cuda.empty_cache()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        log("copy calibration done (3 x 1 GiB)")
+    tr = measured_traffic()
+    if tr:
+        res["roofline"]["traffic"] = tr.get("count_walker_bytes")
+        res["store_roofline"]["traffic"] = tr.get("store_walker_bytes")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(n, g)
