@@ -115,6 +115,51 @@ int fz_count_stream(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
 int fz_unrank(uint64_t n, const uint32_t *g, uint32_t d, const uint64_t *ranks,
               uint64_t nranks, uint32_t *out);
 
+/* ------------------------------------------------------------------------
+ * Batches: many queries (any d, n and consumer) enumerated by one persistent
+ * launch.  Large queries are cut into slices of equal work by their count
+ * tables; small ones are one slice each; all slices of all queries go to one
+ * work queue, so wavefronts that finish one query's slice take the next
+ * slice of any query.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+    FZ_MODE_COUNT = 0,  /* |Z|                                  (fz_count) */
+    FZ_MODE_HIST = 1,   /* length histogram              (fz_length_hist) */
+    FZ_MODE_EXISTS = 2, /* an element of length target_len?   (fz_exists) */
+    FZ_MODE_STORE = 3   /* lex-smallest rows to a device buffer
+                           (fz_enumerate_device) */
+} fz_mode;
+
+typedef struct {
+    uint64_t n;
+    const uint32_t *g;     /* HOST pointer to d generators */
+    uint32_t d;
+    uint32_t mode;         /* fz_mode */
+    uint64_t target_len;   /* FZ_MODE_EXISTS */
+    uint64_t *bins;        /* FZ_MODE_HIST: HOST array of nbins words */
+    uint64_t nbins;        /*   >= fz_length_bins(n, g, d) */
+    uint32_t *d_out;       /* FZ_MODE_STORE: DEVICE buffer of max_tuples rows */
+    uint64_t max_tuples;
+} fz_query;
+
+typedef struct {
+    int status;            /* FZ_OK, FZ_TRUNCATED (store) or a negative error */
+    int found;             /* FZ_MODE_EXISTS */
+    uint64_t count;        /* elements visited (|Z| unless exists stopped early) */
+    uint64_t total;        /* |Z| from the count table, when the query was cut
+                              by it (every store query), else equal to count */
+    uint64_t min_len;      /* FZ_MODE_HIST (UINT64_MAX when Z is empty) */
+    uint64_t max_len;      /* FZ_MODE_HIST (0 when Z is empty) */
+    uint64_t written;      /* FZ_MODE_STORE rows written */
+} fz_result;
+
+/* Runs nq queries as one batch on `stream` (a hipStream_t, NULL: the
+ * library's own) and waits for it.  Returns FZ_OK when the batch ran; each
+ * query's own outcome (including validation errors, which do not stop the
+ * others) is r[i].status.  q and r are HOST arrays of nq entries; FZ_EINVAL
+ * for NULL arrays. */
+int fz_batch(const fz_query *q, fz_result *r, uint32_t nq, void *stream);
+
 /* Work statistics of the last successful enumeration on this device:
  * slices used, rows walked (one row = one prefix a_1..a_{d-3}), prefixes
  * (a_1..a_{d-2}) visited by lanes, candidate steps taken (one per element
@@ -149,11 +194,30 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * knobs. */
 int fz_config_set(const char *key, int64_t value);
 
+/* Autotuner.  Runs the given queries (one fz_batch call when nq > 1, else the
+ * single-query entry point of the query's mode) under every candidate pair of
+ * slices per wave {4, 8, 16, 32, 64} x workgroups per CU {2, 4, 8}, reps
+ * timed runs each after one warm-up, and keeps the pair with the smallest
+ * median wall time as this process's configuration (as fz_config_set would).
+ * The queries' own buffers (bins, store destinations) are overwritten; their
+ * results are not reported.  FZ_EINVAL: NULL q or out, nq == 0, reps outside
+ * 1..100; a failing run returns its status and restores the previous knobs. */
+typedef struct {
+    uint32_t slices_per_wave;
+    uint32_t workgroups_per_cu;
+    double ms;          /* median wall time of the chosen pair */
+    double default_ms;  /* median wall time with the defaults */
+    uint32_t candidates; /* pairs timed */
+} fz_tune_result;
+int fz_autotune(const fz_query *q, uint32_t nq, uint32_t reps, fz_tune_result *out);
+
 /* Kernel timing with HIP events on the launch stream.  fz_profile_enable(1)
  * starts recording (it adds no synchronization of its own); fz_profile_read
  * gives the summed milliseconds and launch count of one kernel ("dp",
  * "restab", "slices", "enum.count", "enum.hist", "enum.exists", "enum.store",
- * "finalize", "unrank") since the last reset. */
+ * "finalize", "unrank"; for fz_batch "batch.prep" (tables, residues and
+ * slice bounds of all queries), "batch.walk", "batch.finalize") since the
+ * last reset. */
 int fz_profile_enable(int on);
 int fz_profile_reset(void);
 int fz_profile_read(const char *kernel, double *total_ms, uint64_t *launches);

@@ -55,6 +55,28 @@ class fz_slice_info(ctypes.Structure):
                 ("t_begin", ctypes.c_uint64), ("t_end", ctypes.c_uint64)]
 
 
+class fz_query(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("g", ctypes.POINTER(ctypes.c_uint32)),
+                ("d", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("target_len", ctypes.c_uint64), ("bins", ctypes.POINTER(ctypes.c_uint64)),
+                ("nbins", ctypes.c_uint64), ("d_out", ctypes.c_void_p),
+                ("max_tuples", ctypes.c_uint64)]
+
+
+class fz_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("found", ctypes.c_int), ("count", ctypes.c_uint64),
+                ("total", ctypes.c_uint64), ("min_len", ctypes.c_uint64),
+                ("max_len", ctypes.c_uint64), ("written", ctypes.c_uint64)]
+
+
+class fz_tune_result(ctypes.Structure):
+    _fields_ = [("slices_per_wave", ctypes.c_uint32), ("workgroups_per_cu", ctypes.c_uint32),
+                ("ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("candidates", ctypes.c_uint32)]
+
+
+MODES = {"count": 0, "hist": 1, "exists": 2, "store": 3}
+
 _u64, _u32, _i64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64
 _u32p = ctypes.POINTER(ctypes.c_uint32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -77,7 +99,10 @@ _SIGS = {
     "fz_profile_reset": (ctypes.c_int, []),
     "fz_profile_read": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), _u64p]),
     "fz_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "fz_batch": (ctypes.c_int, [ctypes.POINTER(fz_query), ctypes.POINTER(fz_result), _u32, _vp]),
     "fz_last_error": (ctypes.c_char_p, []),
+    "fz_autotune": (ctypes.c_int, [ctypes.POINTER(fz_query), _u32, _u32,
+                                   ctypes.POINTER(fz_tune_result)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -176,6 +201,76 @@ def unrank(n: int, g, ranks):
     _check(_lib.fz_unrank(n, gp, len(arr), r.ctypes.data_as(_u64p), len(r), out.ctypes.data_as(_u32p)),
            "fz_unrank")
     return out[: len(r)]
+
+
+def _marshal(queries):
+    """fz_query array for a list of query dicts (see batch); returns it with
+    the host buffers it points to."""
+    nq = len(queries)
+    qarr = (fz_query * max(nq, 1))()
+    keep = []
+    for i, q in enumerate(queries):
+        garr, gp = _gens(q["g"])
+        keep.append(garr)
+        qq = qarr[i]
+        qq.n = q["n"]
+        qq.g = gp
+        qq.d = len(garr)
+        qq.mode = MODES[q["mode"]]
+        qq.target_len = q.get("target_len", 0)
+        if q["mode"] == "hist":
+            nb = q.get("nbins") or max(length_bins(q["n"], q["g"]), 1)
+            bins = np.zeros(nb, dtype=np.uint64)
+            keep.append(bins)
+            qq.bins = bins.ctypes.data_as(_u64p)
+            qq.nbins = nb
+            q["_bins"] = bins
+        if q["mode"] == "store":
+            out = q["out"]
+            if out.dim() != 2 or out.shape[1] != len(garr) or not out.is_contiguous() \
+                    or out.element_size() != 4:
+                raise ValueError("out must be a contiguous [rows, d] tensor of 32-bit integers")
+            qq.d_out = out.data_ptr()
+            qq.max_tuples = q.get("max_tuples", out.shape[0])
+            if qq.max_tuples > out.shape[0]:
+                raise ValueError("max_tuples exceeds the rows of out")
+    return qarr, keep
+
+
+def batch(queries, stream=None):
+    """Run a list of queries as one batch (fz_batch).  Each query is a dict:
+    n, g, mode ('count' | 'hist' | 'exists' | 'store'), target_len (exists),
+    out (store: a contiguous [rows, d] 32-bit CUDA tensor), max_tuples (store,
+    default: out's rows).  Returns one dict per query: status, count, total,
+    found, and bins / min_len / max_len (hist) or written (store)."""
+    nq = len(queries)
+    qarr, keep = _marshal(queries)
+    rarr = (fz_result * max(nq, 1))()
+    _check(_lib.fz_batch(qarr, rarr, nq, _vp(stream) if stream else None), "fz_batch")
+    res = []
+    for i, q in enumerate(queries):
+        r = rarr[i]
+        d = dict(status=r.status, count=r.count, total=r.total, found=bool(r.found))
+        if q["mode"] == "hist":
+            d["bins"] = q.pop("_bins")
+            d["min_len"] = None if r.min_len == 2**64 - 1 else r.min_len
+            d["max_len"] = None if r.min_len == 2**64 - 1 else r.max_len
+        if q["mode"] == "store":
+            d["written"] = r.written
+        res.append(d)
+    return res
+
+
+def autotune(queries, reps: int = 3) -> dict:
+    """fz_autotune: time the queries (one batch, or the single-query path for
+    one query) under each candidate (slices per wave, workgroups per CU) and
+    keep the fastest for this process.  Returns the chosen pair and times."""
+    qarr, keep = _marshal(queries)
+    out = fz_tune_result()
+    _check(_lib.fz_autotune(qarr, len(queries), reps, ctypes.byref(out)), "fz_autotune")
+    for q in queries:
+        q.pop("_bins", None)
+    return {k: getattr(out, k) for k, _ in fz_tune_result._fields_}
 
 
 def last_stats() -> dict:

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -22,6 +24,7 @@ constexpr uint32_t kDefaultWgPerCu = 8;
 constexpr uint32_t kMaxSlices = 1u << 22;
 constexpr size_t kLdsHistBudget = 64 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
+constexpr uint32_t kBatchLdsBins = 1024;         // per-wave LDS histogram in batches
 // Work model of the walker for cutting slices, in 1/64 of a wave instruction
 // (measured on the compiled walker): a row costs about 50 instructions (the
 // odometer step and the row bounds), a 64-lane chunk about 23 plus one trip
@@ -45,6 +48,11 @@ struct Ctx {
     hipStream_t stream = nullptr;
     FzCtl *host_ctl = nullptr; // pinned
     DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out;
+    // batches
+    DevBuf b_meta, b_tables, b_restabs, b_bounds, b_base, b_recs, b_bins, b_res, b_cursor;
+    std::vector<uint8_t> b_host;
+    FzBatchResult *b_res_host = nullptr; // pinned
+    size_t b_res_cap = 0;
     fz_stats last{};
 };
 
@@ -266,8 +274,8 @@ void prof_collect()
             e.ms += ms;
             e.n += 1;
         }
-        hipEventDestroy(p.a);
-        hipEventDestroy(p.b);
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
     }
     g_pending.clear();
 }
@@ -286,7 +294,7 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
     P.hist_in_lds = (P.mode == FZM_HIST) &&
-                    ((size_t)(FZK_WG / FZK_WAVE) * (P.nbins + FZK_WAVE) * 4 <= kLdsHistBudget);
+                    ((size_t)(FZK_WG / FZK_WAVE) * P.nbins * 8 <= kLdsHistBudget);
     const uint64_t table_words = (uint64_t)(P.d - 1) * P.stride;
     const uint64_t cost_words = (uint64_t)(P.d - 2) * P.stride;
     FZ_TRY(ensure(c.S, table_words * 8));
@@ -401,9 +409,241 @@ int do_enumerate(uint64_t n, const uint32_t *g, uint32_t d, uint32_t *out, bool 
     return wr < N ? FZ_TRUNCATED : FZ_OK;
 }
 
+// Rough work of a query in the walker's units (row, chunk and element
+// weights of its plan), from the leading terms of the counts of rows, lane
+// prefixes and elements: a set {a : sum_{i<k} a_i g_i <= v} has about
+// v^k / (k! prod g_i) points.  Only used to decide how finely to cut.
+double estimate_work(const FzPlan &P)
+{
+    const uint32_t M = P.d - 3;
+    const double ln1 = std::log((double)P.n + 1.0);
+    double lg_rows = 0, lg_pref = 0, lg_el = 0;
+    for (uint32_t k = 0; k < M; ++k) lg_rows -= std::log((double)P.g[k]);
+    lg_pref = lg_rows - std::log((double)P.g[M]);
+    lg_el = lg_pref - std::log((double)P.g[M + 1]) - std::log((double)P.g[M + 2]);
+    lg_rows += M * ln1 - std::lgamma(M + 1.0);
+    lg_pref += (M + 1) * ln1 - std::lgamma(M + 2.0);
+    lg_el += (M + 2) * ln1 - std::lgamma(M + 3.0);
+    const double rows = std::exp(std::min(lg_rows, 200.0));
+    const double pref = std::exp(std::min(lg_pref, 200.0));
+    const double el = std::exp(std::min(lg_el, 200.0));
+    return P.w_row * std::max(rows, 1.0) + P.w_chunk * (pref / FZK_WAVE + std::max(rows, 1.0)) +
+           P.w_el * el;
+}
+
+template <class T> T *stage(std::vector<uint8_t> &buf, size_t &off, size_t count)
+{
+    off = (off + 63) & ~(size_t)63;
+    T *p = (T *)(buf.data() + off);
+    off += count * sizeof(T);
+    return p;
+}
+
+int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *cp;
+    int rc = get_ctx(&cp);
+    if (rc) return rc;
+    Ctx &c = *cp;
+    hipStream_t st = stream ? (hipStream_t)stream : c.stream;
+
+    // plans; a rejected query keeps d = 0 and takes no device work
+    std::vector<FzBatchQuery> Q(nq);
+    std::vector<int> qst(nq, FZ_OK);
+    std::vector<double> work(nq, 0.0);
+    double total_work = 0;
+    uint32_t maxm = 0, max_du = 0, bstride = 1;
+    bool any_hist = false;
+    for (uint32_t i = 0; i < nq; ++i) {
+        std::memset(&Q[i], 0, sizeof(FzBatchQuery));
+        const fz_query &q = qs[i];
+        if (q.mode > FZ_MODE_STORE) { qst[i] = FZ_EINVAL; continue; }
+        FzPlan &P = Q[i].plan;
+        int e = make_plan(q.n, q.g, q.d, q.mode, &P);
+        if (!e && q.mode == FZ_MODE_HIST && (q.bins == nullptr || q.nbins < P.nbins)) e = FZ_EINVAL;
+        if (!e && q.mode == FZ_MODE_STORE && q.d_out == nullptr && q.max_tuples > 0) e = FZ_EINVAL;
+        if (e) {
+            qst[i] = e;
+            std::memset(&P, 0, sizeof P);
+            continue;
+        }
+        P.target_len = q.target_len;
+        if (q.mode == FZ_MODE_STORE) P.max_tuples = q.max_tuples;
+        work[i] = estimate_work(P);
+        total_work += work[i];
+        maxm = std::max(maxm, P.d - 3);
+        bstride = std::max(bstride, P.d - 2);
+        if (q.mode == FZ_MODE_STORE) max_du = std::max(max_du, P.d_user);
+        if (q.mode == FZ_MODE_HIST) any_hist = true;
+    }
+    const uint32_t wgcu = g_wg_per_cu ? g_wg_per_cu : kDefaultWgPerCu;
+    const uint32_t spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
+    const double waves = (double)c.cus * wgcu * (FZK_WG / FZK_WAVE);
+    const double target = std::max(total_work / (waves * spw), 1.0);
+    const uint32_t lds_bins = any_hist ? kBatchLdsBins : 0;
+
+    // cut: a query worth more than two target slices gets count and work
+    // tables and W_q slices; stores always get tables (their rows are placed
+    // by rank).  Items of large queries first, then the rest by falling work.
+    std::vector<uint32_t> order;
+    for (uint32_t i = 0; i < nq; ++i)
+        if (Q[i].plan.d) order.push_back(i);
+    uint64_t tab_words = 0, res_words = 0, bin_words = 0;
+    uint32_t n_items = 0, n_bounds = 0;
+    std::vector<uint32_t> sliced_ids;
+    for (uint32_t i : order) {
+        FzBatchQuery &B = Q[i];
+        FzPlan &P = B.plan;
+        const double w = work[i] / target;
+        B.sliced = (P.mode == FZM_STORE || w > 2.0) ? 1 : 0;
+        B.n_slices = B.sliced ? (uint32_t)std::min(std::max(std::ceil(w), 1.0), 65536.0) : 1;
+        P.n_slices = B.n_slices;
+        P.hist_in_lds = P.mode == FZM_HIST && P.nbins <= lds_bins;
+        P.restab_in_lds = 0;
+        if (B.sliced) {
+            B.s_off = tab_words;
+            tab_words += (uint64_t)(P.d - 1) * P.stride;
+            B.c_off = tab_words;
+            tab_words += (uint64_t)(P.d - 2) * P.stride;
+            sliced_ids.push_back(i);
+        }
+        B.tab_off = res_words;
+        res_words += 2 * (uint64_t)P.B;
+        if (P.mode == FZM_HIST) {
+            B.bins_off = bin_words;
+            bin_words += P.nbins;
+        }
+        B.out = qs[i].d_out;
+        B.bound_off = n_bounds;
+        n_bounds += B.n_slices + 1;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (Q[a].sliced != Q[b].sliced) return Q[a].sliced > Q[b].sliced;
+        return work[a] / Q[a].n_slices > work[b] / Q[b].n_slices;
+    });
+    for (uint32_t i : order) {
+        Q[i].item_off = n_items;
+        n_items += Q[i].n_slices;
+    }
+
+    // host staging: queries, boundary jobs, items, ids of sliced queries
+    size_t off = 0;
+    c.b_host.resize(64 + nq * sizeof(FzBatchQuery) + (size_t)n_bounds * sizeof(FzBatchJob) +
+                    (size_t)n_items * sizeof(FzBatchJob) + sliced_ids.size() * 4 + 4 * 64);
+    FzBatchQuery *hq = stage<FzBatchQuery>(c.b_host, off, nq);
+    const size_t o_jobs = (off + 63) & ~(size_t)63;
+    FzBatchJob *hj = stage<FzBatchJob>(c.b_host, off, n_bounds);
+    const size_t o_items = (off + 63) & ~(size_t)63;
+    FzBatchJob *hi = stage<FzBatchJob>(c.b_host, off, n_items);
+    const size_t o_ids = (off + 63) & ~(size_t)63;
+    uint32_t *hids = stage<uint32_t>(c.b_host, off, sliced_ids.size());
+    std::memcpy(hq, Q.data(), nq * sizeof(FzBatchQuery));
+    for (uint32_t i : order) {
+        for (uint32_t j = 0; j <= Q[i].n_slices; ++j) hj[Q[i].bound_off + j] = {i, j};
+        for (uint32_t j = 0; j < Q[i].n_slices; ++j) hi[Q[i].item_off + j] = {i, j};
+    }
+    std::memcpy(hids, sliced_ids.data(), sliced_ids.size() * 4);
+
+    FZ_TRY(ensure(c.b_meta, off));
+    FZ_TRY(ensure(c.b_tables, tab_words * 8));
+    FZ_TRY(ensure(c.b_restabs, res_words * sizeof(int2)));
+    FZ_TRY(ensure(c.b_bounds, (size_t)n_bounds * bstride * 4));
+    FZ_TRY(ensure(c.b_base, (size_t)n_bounds * 8));
+    FZ_TRY(ensure(c.b_recs, (size_t)std::max(n_items, 1u) * sizeof(FzSliceRec)));
+    FZ_TRY(ensure(c.b_bins, bin_words * 8));
+    FZ_TRY(ensure(c.b_res, (size_t)nq * sizeof(FzBatchResult)));
+    FZ_TRY(ensure(c.b_cursor, 256));
+    if (c.b_res_cap < nq) {
+        if (c.b_res_host) (void)hipHostFree(c.b_res_host);
+        c.b_res_host = nullptr;
+        c.b_res_cap = 0;
+        FZ_TRY(hipHostMalloc((void **)&c.b_res_host, (size_t)nq * sizeof(FzBatchResult),
+                             hipHostMallocDefault));
+        c.b_res_cap = nq;
+    }
+    uint8_t *meta = (uint8_t *)c.b_meta.p;
+    FZ_TRY(hipMemcpyAsync(meta, c.b_host.data(), off, hipMemcpyHostToDevice, st));
+
+    FzBatchBufs B;
+    B.queries = (const FzBatchQuery *)meta;
+    B.bjobs = (const FzBatchJob *)(meta + o_jobs);
+    B.items = (const FzBatchJob *)(meta + o_items);
+    B.tables = (uint64_t *)c.b_tables.p;
+    B.restabs = (int2 *)c.b_restabs.p;
+    B.bounds = (uint32_t *)c.b_bounds.p;
+    B.base = (uint64_t *)c.b_base.p;
+    B.recs = (FzSliceRec *)c.b_recs.p;
+    B.bins = (uint64_t *)c.b_bins.p;
+    B.res = (FzBatchResult *)c.b_res.p;
+    B.cursor = (uint32_t *)c.b_cursor.p;
+    B.nq = nq;
+    B.n_bjobs = n_bounds;
+    B.n_items = n_items;
+    B.bstride = bstride;
+    B.n_bins = bin_words;
+    const uint32_t nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
+                                                      std::max<uint32_t>(1, (n_items + 3) / 4));
+    FZ_LAUNCH("batch.prep", st,
+              fzk_launch_batch_prep(B, (uint32_t)sliced_ids.size(),
+                                    (const uint32_t *)(meta + o_ids), st));
+    FZ_LAUNCH("batch.walk", st, fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
+    FZ_LAUNCH("batch.finalize", st, fzk_launch_batch_finalize(B, st));
+    FZ_TRY(hipMemcpyAsync(c.b_res_host, B.res, (size_t)nq * sizeof(FzBatchResult),
+                          hipMemcpyDeviceToHost, st));
+    std::vector<uint64_t> bins(bin_words);
+    if (bin_words)
+        FZ_TRY(hipMemcpyAsync(bins.data(), B.bins, bin_words * 8, hipMemcpyDeviceToHost, st));
+    FZ_TRY(hipStreamSynchronize(st));
+    prof_collect();
+
+    for (uint32_t i = 0; i < nq; ++i) {
+        fz_result &r = rs[i];
+        std::memset(&r, 0, sizeof r);
+        r.min_len = UINT64_MAX;
+        if (qst[i]) {
+            r.status = qst[i];
+            continue;
+        }
+        const FzBatchResult &h = c.b_res_host[i];
+        const FzPlan &P = Q[i].plan;
+        if (h.status & FZS_OVERFLOW) { r.status = FZ_EOVERFLOW; continue; }
+        if (h.status & FZS_MISMATCH) { r.status = FZ_EINTERNAL; continue; }
+        r.count = h.count;
+        r.total = Q[i].sliced ? h.total : h.count;
+        r.found = h.found ? 1 : 0;
+        r.status = FZ_OK;
+        if (P.mode == FZM_HIST) {
+            uint64_t sum = 0;
+            for (uint32_t l = 0; l < P.nbins; ++l) sum += bins[Q[i].bins_off + l];
+            if (sum != h.count) { r.status = FZ_EINTERNAL; continue; }
+            std::memcpy(qs[i].bins, bins.data() + Q[i].bins_off, (size_t)P.nbins * 8);
+            for (uint64_t l = P.nbins; l < qs[i].nbins; ++l) qs[i].bins[l] = 0;
+            r.min_len = h.count ? h.min_len : UINT64_MAX;
+            r.max_len = h.count ? h.max_len : 0;
+        }
+        if (P.mode == FZM_STORE) {
+            r.written = h.count;
+            if (h.count != std::min(h.total, P.max_tuples)) { r.status = FZ_EINTERNAL; continue; }
+            if (h.total > P.max_tuples) r.status = FZ_TRUNCATED;
+        }
+        if (P.mode == FZM_COUNT && Q[i].sliced && h.count != h.total) r.status = FZ_EINTERNAL;
+    }
+    c.last.slices = n_items;
+    return FZ_OK;
+}
+
 } // namespace
 
 extern "C" {
+
+int fz_batch(const fz_query *q, fz_result *r, uint32_t nq, void *stream)
+{
+    if ((q == nullptr || r == nullptr) && nq > 0) return FZ_EINVAL;
+    if (nq == 0) return FZ_OK;
+    return do_batch(q, r, nq, stream);
+}
+
 
 int fz_count(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count)
 {
@@ -559,6 +799,92 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "work_chunk") == 0) g_work_chunk = (uint32_t)value;
     else if (std::strcmp(key, "work_element") == 0) g_work_elem = (uint32_t)value;
     else return FZ_EINVAL;
+    return FZ_OK;
+}
+
+namespace {
+// One timed run of the autotuner: wall milliseconds of a synchronous call.
+int tune_run(const fz_query *q, uint32_t nq, std::vector<fz_result> &r, double *ms)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = FZ_OK;
+    if (nq > 1) {
+        rc = fz_batch(q, r.data(), nq, nullptr);
+    } else {
+        const fz_query &x = q[0];
+        uint64_t a = 0, b = 0;
+        int f = 0;
+        switch (x.mode) {
+        case FZ_MODE_COUNT: rc = fz_count(x.n, x.g, x.d, &a); break;
+        case FZ_MODE_HIST: rc = fz_length_hist(x.n, x.g, x.d, x.bins, x.nbins, &a, &b); break;
+        case FZ_MODE_EXISTS: rc = fz_exists(x.n, x.g, x.d, x.target_len, &f); break;
+        case FZ_MODE_STORE:
+            rc = fz_enumerate_device(x.n, x.g, x.d, x.d_out, x.max_tuples, &a, &b, nullptr);
+            break;
+        default: rc = FZ_EINVAL;
+        }
+    }
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return rc < 0 ? rc : FZ_OK;
+}
+} // namespace
+
+int fz_autotune(const fz_query *q, uint32_t nq, uint32_t reps, fz_tune_result *out)
+{
+    if (q == nullptr || out == nullptr || nq == 0 || reps == 0 || reps > 100) return FZ_EINVAL;
+    static const uint32_t kSpw[] = {4, 8, 16, 32, 64};
+    static const uint32_t kWg[] = {2, 4, 8};
+    uint32_t save_spw, save_wg;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        save_spw = g_slices_per_wave;
+        save_wg = g_wg_per_cu;
+    }
+    auto set = [](uint32_t spw, uint32_t wg) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_slices_per_wave = spw;
+        g_wg_per_cu = wg;
+    };
+    std::vector<fz_result> r(nq);
+    auto median = [&](uint32_t spw, uint32_t wg, double *ms) -> int {
+        set(spw, wg);
+        double t;
+        int rc = tune_run(q, nq, r, &t); // warm-up
+        std::vector<double> v;
+        for (uint32_t i = 0; rc == FZ_OK && i < reps; ++i) {
+            rc = tune_run(q, nq, r, &t);
+            v.push_back(t);
+        }
+        if (rc != FZ_OK) return rc;
+        std::sort(v.begin(), v.end());
+        *ms = v[v.size() / 2];
+        return FZ_OK;
+    };
+    fz_tune_result best{};
+    int rc = median(0, 0, &best.default_ms);
+    best.slices_per_wave = kDefaultSlicesPerWave;
+    best.workgroups_per_cu = kDefaultWgPerCu;
+    best.ms = best.default_ms;
+    best.candidates = 1;
+    for (uint32_t spw : kSpw)
+        for (uint32_t wg : kWg) {
+            if (rc != FZ_OK) break;
+            if (spw == kDefaultSlicesPerWave && wg == kDefaultWgPerCu) continue;
+            double ms = 0;
+            rc = median(spw, wg, &ms);
+            ++best.candidates;
+            if (rc == FZ_OK && ms < best.ms) {
+                best.ms = ms;
+                best.slices_per_wave = spw;
+                best.workgroups_per_cu = wg;
+            }
+        }
+    if (rc != FZ_OK) {
+        set(save_spw, save_wg);
+        return rc;
+    }
+    set(best.slices_per_wave, best.workgroups_per_cu);
+    *out = best;
     return FZ_OK;
 }
 

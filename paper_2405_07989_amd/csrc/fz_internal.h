@@ -97,6 +97,57 @@ struct FzBufs {
     uint32_t *out;        // store destination (row-major [.][d_user])
 };
 
+// ---------------------------------------------------------------------------
+// Batches: many queries walked by one persistent launch.  Each query has a
+// plan and the offsets of its device data; its work is cut into W_q slices
+// (W_q = 1 for queries too small to be worth a count table: their one slice
+// runs from the prefix (0,...,0) to the end of the set).
+// ---------------------------------------------------------------------------
+struct FzBatchQuery {
+    FzPlan plan;
+    uint64_t s_off;       // count table (rows 0..d-2), when sliced
+    uint64_t c_off;       // work table (rows 0..M), when sliced
+    uint64_t tab_off;     // residue table (2B int2)
+    uint64_t bins_off;    // histogram bins (nbins u64), hist queries
+    uint32_t *out;        // store destination (device), store queries
+    uint32_t sliced;      // 1: count/work tables and W_q rank-cut slices
+    uint32_t n_slices;    // W_q
+    uint32_t bound_off;   // first boundary of this query in the bounds array
+    uint32_t item_off;    // first walker item of this query
+};
+
+// Per-query result in device memory.
+struct FzBatchResult {
+    uint64_t count;       // elements the walkers visited
+    uint64_t total;       // |Z| from the count table (sliced queries)
+    uint64_t min_len, max_len;
+    uint64_t written;
+    uint32_t found;
+    uint32_t status;      // FZS_* bits
+};
+
+// A boundary job of the batch slice kernel / a walker work item.
+struct FzBatchJob {
+    uint32_t q;           // query index
+    uint32_t j;           // slice index within the query (boundary j for jobs)
+};
+
+struct FzBatchBufs {
+    const FzBatchQuery *queries;
+    const FzBatchJob *bjobs;   // boundary jobs: sum over queries of (W_q + 1)
+    const FzBatchJob *items;   // walker items: sum over queries of W_q
+    uint64_t *tables;          // count and work tables of sliced queries
+    int2 *restabs;             // residue tables
+    uint32_t *bounds;          // boundaries, stride bstride words
+    uint64_t *base;            // element rank of each boundary
+    FzSliceRec *recs;          // per item
+    uint64_t *bins;            // histogram bins of hist queries
+    FzBatchResult *res;        // per query
+    uint32_t *cursor;          // walker item cursor (own 128-byte line)
+    uint32_t nq, n_bjobs, n_items, bstride;
+    uint64_t n_bins;           // words of the histogram buffer
+};
+
 // Launchers (fz_kernels.hip).
 #include <hip/hip_runtime.h>
 hipError_t fzk_launch_dp(const FzPlan &p, const FzBufs &b, hipStream_t s);
@@ -107,3 +158,10 @@ hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, h
 hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *ranks,
                              uint64_t nranks, uint32_t *out, hipStream_t s);
 size_t fzk_enum_lds_bytes(const FzPlan &p);
+// batch: zeroing, count / work tables, residue tables and slice bounds; then
+// the persistent walker; then the per-query finalize
+hipError_t fzk_launch_batch_prep(const FzBatchBufs &b, uint32_t n_sliced,
+                                 const uint32_t *sliced_ids, hipStream_t s);
+hipError_t fzk_launch_batch_walk(const FzBatchBufs &b, uint32_t maxm, uint32_t nwg,
+                                 uint32_t lds_bins, uint32_t max_du, hipStream_t s);
+hipError_t fzk_launch_batch_finalize(const FzBatchBufs &b, hipStream_t s);

@@ -1,13 +1,15 @@
 // fz_kernels.hip -- HIP kernels of libfz for gfx950 (CDNA4, wave64).
 //
-//   fz_dp_kernel        count table S[k][v] (completions of a prefix)
+//   fz_dp_kernel        count table S[k][v] (completions of a prefix) and the
+//                       work table used to cut slices
 //   fz_restab_kernel    first element of the last-pair progression per
 //                       residue class of the remainder modulo g[d-1]
-//   fz_slices_kernel    rank-balanced slice bounds (Sec. 4 bounds, cut by rank)
+//   fz_slices_kernel    slice bounds cut to equal work (Sec. 4 bounds)
 //   fz_enum_kernel      the walker: bounded lexicographic enumeration with a
 //                       count / length-histogram / predicate / store consumer
 //   fz_finalize_kernel  sums, the slice self-check, histogram reduction
 //   fz_unrank_kernel    element of a given rank (the fz_unrank entry point)
+//   fz_batch_*          the same steps for many queries in one launch each
 //
 // Layout and notation are described in fz_internal.h.
 #include <hip/hip_runtime.h>
@@ -123,13 +125,18 @@ __device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM
     return (P.w_el && we / P.w_el != el) ? ~0ull : sat_add(w, we);
 }
 
-template <class Below>
-__device__ void chain_scan(const FzPlan &P, uint64_t *row, uint32_t gk, Below below,
-                           uint64_t *part)
+// Running sums along the chains v = c, c + gk, c + 2 gk, ... < len of
+// below(v), written to row[v]; in place is allowed (row[v] is written only
+// by the thread that read below(v)).  SAT: saturating adds (count tables);
+// else wrapping adds (the histogram's difference array, whose entries may be
+// negative in two's complement).
+template <bool SAT, class Below>
+__device__ void chain_scan(uint64_t *row, uint32_t len, uint32_t gk, Below below, uint64_t *part)
 {
+    const auto add = [](uint64_t a, uint64_t b) { return SAT ? sat_add(a, b) : a + b; };
     const uint32_t T = blockDim.x, tid = threadIdx.x;
-    const uint32_t rows = P.n / gk + 1;
-    const uint32_t cols = gk < P.stride ? gk : P.stride;
+    const uint32_t rows = (len - 1) / gk + 1;
+    const uint32_t cols = gk < len ? gk : len;
     const uint32_t nb = cols >= T ? 1 : T / cols;
     const uint32_t rpb = (rows + nb - 1) / nb;
     const uint32_t units = cols * nb;
@@ -144,10 +151,10 @@ __device__ void chain_scan(const FzPlan &P, uint64_t *row, uint32_t gk, Below be
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
                     const uint64_t v = (uint64_t)(i + q) * gk + c;
-                    x[q] = (i + q < i1 && v <= P.n) ? below((uint32_t)v) : 0;
+                    x[q] = (i + q < i1 && v < len) ? below((uint32_t)v) : 0;
                 }
 #pragma unroll
-                for (int q = 0; q < 8; ++q) s = sat_add(s, x[q]);
+                for (int q = 0; q < 8; ++q) s = add(s, x[q]);
             }
             part[u] = s;
         }
@@ -157,7 +164,7 @@ __device__ void chain_scan(const FzPlan &P, uint64_t *row, uint32_t gk, Below be
             for (uint32_t b = 0; b < nb; ++b) {
                 const uint64_t t = part[b * cols + c];
                 part[b * cols + c] = carry;
-                carry = sat_add(carry, t);
+                carry = add(carry, t);
             }
         }
         __syncthreads();
@@ -171,44 +178,50 @@ __device__ void chain_scan(const FzPlan &P, uint64_t *row, uint32_t gk, Below be
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint64_t v = (uint64_t)(i + q) * gk + c;
-                x[q] = (i + q < i1 && v <= P.n) ? below((uint32_t)v) : 0;
+                x[q] = (i + q < i1 && v < len) ? below((uint32_t)v) : 0;
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint64_t v = (uint64_t)(i + q) * gk + c;
-                run = sat_add(run, x[q]);
-                if (i + q < i1 && v <= P.n) row[v] = run;
+                run = add(run, x[q]);
+                if (i + q < i1 && v < len) row[v] = run;
             }
         }
     }
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
+// All rows of S (k = d-2..0) and of the work table C (k = M..0) for one
+// query; called by a whole workgroup of 1024 threads.
+__device__ void dp_query(const FzPlan &P, uint64_t *S, uint64_t *C, uint64_t *part)
 {
-    __shared__ uint64_t part[1024];
-    uint64_t *S = Bf.S;
     for (int k = (int)P.d - 2; k >= 0; --k) {
         uint64_t *row = S + (uint64_t)k * P.stride;
         const uint64_t *nxt = S + (uint64_t)(k + 1) * P.stride;
         if (k + 1 == (int)P.d - 1)
-            chain_scan(P, row, P.g[k],
-                       [&](uint32_t v) { return (v - fdiv(v, P.div_B) * P.B) == 0 ? 1ull : 0ull; },
-                       part);
+            chain_scan<true>(
+                row, P.stride, P.g[k],
+                [&](uint32_t v) { return (v - fdiv(v, P.div_B) * P.B) == 0 ? 1ull : 0ull; }, part);
         else
-            chain_scan(P, row, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
+            chain_scan<true>(row, P.stride, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
     }
     const int M = (int)P.d - 3;
-    uint64_t *CM = Bf.C + (uint64_t)M * P.stride;
+    uint64_t *CM = C + (uint64_t)M * P.stride;
     const uint64_t *SM = S + (uint64_t)M * P.stride;
     for (uint32_t v = threadIdx.x; v <= P.n; v += blockDim.x)
         CM[v] = row_work(P, SM, v, fdiv(v, P.div_G2) + 1);
     __syncthreads();
     for (int k = M - 1; k >= 0; --k) {
-        uint64_t *row = Bf.C + (uint64_t)k * P.stride;
-        const uint64_t *nxt = Bf.C + (uint64_t)(k + 1) * P.stride;
-        chain_scan(P, row, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
+        uint64_t *row = C + (uint64_t)k * P.stride;
+        const uint64_t *nxt = C + (uint64_t)(k + 1) * P.stride;
+        chain_scan<true>(row, P.stride, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
     }
+}
+
+__global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
+{
+    __shared__ uint64_t part[1024];
+    dp_query(P, Bf.S, Bf.C, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -220,10 +233,8 @@ __global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
 // that a lane can index it with rho' = rho + B in [0, 2B) and quotient
 // q' = q - 1 without a borrow: entry rho' >= B holds E(rho' - B) - 1.
 // ---------------------------------------------------------------------------
-__global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
+__device__ __forceinline__ int2 restab_entry(const FzPlan &P, uint32_t i)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 2 * P.B) return;
     const uint32_t rho = i < P.B ? i : i - P.B;
     int2 e;
     if (rho % P.D != 0) {
@@ -236,7 +247,13 @@ __global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
         e.y = (int)(num / P.B);
         if (i >= P.B) e.y -= 1;
     }
-    Bf.restab[i] = e;
+    return e;
+}
+
+__global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 2 * P.B) Bf.restab[i] = restab_entry(P, i);
 }
 
 // ---------------------------------------------------------------------------
@@ -249,45 +266,31 @@ __global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
 // [bound j, bound j+1); base[j] is the element rank of its first element.
 // Boundary W is open (sentinel).  Thread 0 also resets the control block.
 // ---------------------------------------------------------------------------
-__global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
+// Boundary j of a query cut into W slices: writes its prefix a[0..M] (or the
+// sentinel) to out and returns the element rank of its first element.
+__device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64_t *C, uint32_t W,
+                                uint32_t j, uint32_t *out)
 {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t W = P.n_slices;
-    const uint32_t np = P.d - 2;
     const uint32_t M = P.d - 3;
-    const uint64_t N = Bf.S[P.n];
-    const bool ovf = (N == ~0ull) || (Bf.C[P.n] == ~0ull);
-    if (j == 0) {
-        FzCtl *c = Bf.ctl;
-        c->cursor = 0;
-        c->found = 0;
-        c->status = ovf ? FZS_OVERFLOW : 0u;
-        c->total = N;
-        c->count = 0;
-        c->rows = 0;
-        c->prefixes = 0;
-        c->written = 0;
-    }
-    if (j > W) return;
+    const uint64_t N = S[P.n];
+    const bool ovf = (N == ~0ull) || (C[P.n] == ~0ull);
     const uint64_t Np = ovf ? 0 : (N < P.max_tuples ? N : P.max_tuples);
-    uint32_t *out = Bf.bounds + (uint64_t)j * np;
-    if (j == W || Np == 0) {
-        Bf.base[j] = Np;
+    if (j >= W || Np == 0) {
         out[0] = FZK_SENTINEL;
-        return;
+        return Np;
     }
-    const uint64_t *SM = Bf.S + (uint64_t)M * P.stride;
+    const uint64_t *SM = S + (uint64_t)M * P.stride;
     uint64_t Wtot;
     if (Np == N) {
-        Wtot = Bf.C[P.n];
+        Wtot = C[P.n];
     } else {
         // work of the rows before the one that holds element rank Np-1, plus
         // that row up to and including the lane holding it
         uint64_t r = Np - 1, acc = 0;
         uint32_t v = P.n;
         for (uint32_t k = 0; k < M; ++k) {
-            const uint64_t *Ck = Bf.C + (uint64_t)k * P.stride;
-            const uint32_t t = unrank_level(Bf.S + (uint64_t)k * P.stride, v, P.g[k], r);
+            const uint64_t *Ck = C + (uint64_t)k * P.stride;
+            const uint32_t t = unrank_level(S + (uint64_t)k * P.stride, v, P.g[k], r);
             acc += Ck[v] - Ck[v - t * P.g[k]];
             v -= t * P.g[k];
         }
@@ -298,8 +301,8 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
     uint64_t base = 0;
     uint32_t v = P.n;
     for (uint32_t k = 0; k < M; ++k) {
-        const uint64_t *Sk = Bf.S + (uint64_t)k * P.stride;
-        const uint32_t t = unrank_level(Bf.C + (uint64_t)k * P.stride, v, P.g[k], rc);
+        const uint64_t *Sk = S + (uint64_t)k * P.stride;
+        const uint32_t t = unrank_level(C + (uint64_t)k * P.stride, v, P.g[k], rc);
         base += Sk[v] - Sk[v - t * P.g[k]];
         out[k] = t;
         v -= t * P.g[k];
@@ -313,21 +316,308 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
     }
     out[M] = lo;
     base += SM[v] - SM[v - lo * P.G2];
-    Bf.base[j] = base;
+    return base;
+}
+
+__global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
+{
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t W = P.n_slices;
+    if (j == 0) {
+        const uint64_t N = Bf.S[P.n];
+        const bool ovf = (N == ~0ull) || (Bf.C[P.n] == ~0ull);
+        FzCtl *c = Bf.ctl;
+        c->cursor = 0;
+        c->found = 0;
+        c->status = ovf ? FZS_OVERFLOW : 0u;
+        c->total = N;
+        c->count = 0;
+        c->rows = 0;
+        c->prefixes = 0;
+        c->written = 0;
+    }
+    if (j > W) return;
+    Bf.base[j] = slice_bound(P, Bf.S, Bf.C, W, j, Bf.bounds + (uint64_t)j * (P.d - 2));
 }
 
 // ---------------------------------------------------------------------------
-// The walker.  Persistent workgroups of four waves; each wave takes slices
-// from an atomic cursor.  Within a slice the row prefix a[0..M-1] is a
-// wave-uniform odometer in ascending lex order (scalar registers); a row is
-// cut into chunks of 64 consecutive values of the lane coordinate x = a[M];
-// each lane solves its last pair from the residue table and then steps its
-// progression of elements one candidate at a time (the modulo skip of
-// Sec. 3.2.4: a[d-2] += ord, a[d-1] -= delta), the step ending at the first
-// candidate with a[d-1] < 0.  The consumer sees every element.
+// The walker.  Within a slice the row prefix a[0..M-1] is a wave-uniform
+// odometer in ascending lex order (scalar registers); a row is cut into
+// chunks of 64 consecutive values of the lane coordinate x = a[M]; each lane
+// solves its last pair from the residue table and then steps its progression
+// of elements one candidate at a time (the modulo skip of Sec. 3.2.4:
+// a[d-2] += ord, a[d-1] -= delta), the step ending at the first candidate
+// with a[d-1] < 0.  The consumer sees every element.
 //
-// LDS: [residue table, 2B int2, when it fits][per-wave consumer scratch].
+// walk_slice walks one slice [b0, b1) for one wave.  MAXM bounds the row
+// depth M (M == MAXM in the single-query kernel, where it is a compile-time
+// constant; the batch kernel passes each query's own M <= MAXM).
 // ---------------------------------------------------------------------------
+struct WalkIO {
+    const int2 *ltab;   // residue table staged in LDS (TLDS)
+    const int2 *gtab;   // residue table in global memory (!TLDS)
+    uint64_t *wbins;    // this wave's LDS histogram (difference array)
+    uint64_t *gbins;    // the global histogram (bins not in LDS)
+    uint32_t *found;    // predicate flag (early exit)
+    uint32_t *out;      // store destination, row-major [.][d_user]
+    uint64_t *s_incl;   // store scratch of this wave: scan, t0, ad0, rows
+    uint32_t *s_t0, *s_ad0, *s_stage;
+};
+
+struct WalkOut {
+    uint64_t elements, rows, prefixes;
+};
+
+// One run of a lane: cnt elements with lengths len0, len0 + step, ...
+// Recorded in the histogram's strided difference array (stride |step|): +1
+// at the run's shortest length and -1 one stride past its longest; with
+// step 0 all cnt elements have length len0.  Bins are 64-bit and wrap
+// modulo 2^64, so negative entries are two's complement.
+__device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint32_t len0,
+                                         uint32_t cnt, int32_t step)
+{
+    uint32_t lo = len0, inc = cnt;
+    uint64_t hi = ~0ull;
+    if (step != 0) {
+        const uint32_t mag = step > 0 ? (uint32_t)step : (uint32_t)-step;
+        if (step < 0) lo = len0 - (cnt - 1) * mag;
+        hi = (uint64_t)lo + (uint64_t)cnt * mag;
+        inc = 1;
+    }
+    if (P.hist_in_lds) {
+        atomicAdd((unsigned long long *)&io.wbins[lo], (unsigned long long)inc);
+        if (hi < P.nbins) atomicAdd((unsigned long long *)&io.wbins[hi], ~0ull);
+    } else {
+        atomicAdd((unsigned long long *)&io.gbins[lo], (unsigned long long)inc);
+        if (hi < P.nbins) atomicAdd((unsigned long long *)&io.gbins[hi], ~0ull);
+    }
+}
+
+template <int MAXM, int MODE, bool TLDS>
+__device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
+                                              const uint32_t *b0, const uint32_t *b1,
+                                              uint64_t rank, const WalkIO &io, uint32_t lane)
+{
+    // lane * G2 = lq * B + lr (exact whenever the lane is active).  A lane
+    // reads the doubled residue table at rho' = Pc + (B - lr) with quotient
+    // q' = Qc - (lq + 1): no borrow to propagate.
+    const uint64_t lg = (uint64_t)lane * P.G2;
+    const uint32_t lq1 = (uint32_t)(lg / P.B) + 1;
+    const uint32_t lr2 = P.B - (uint32_t)(lg % P.B);
+    const uint32_t len_step = P.ord - P.delta;
+    const int32_t delta = (int32_t)P.delta;
+    // lengths are < 2^31, so a target beyond 32 bits matches none
+    const uint32_t target = P.target_len >> 32 ? FZK_SENTINEL : (uint32_t)P.target_len;
+    // per-lane element counters: a chunk adds at most n + 1 per lane to the
+    // 32-bit counter, which is folded into the 64-bit one per chunk
+    uint64_t lane_el = 0;
+    uint32_t lane_pref = 0;
+    uint64_t n_el = 0, n_rows = 0;
+    if (uni(b0[0]) != FZK_SENTINEL) {
+        uint32_t a[MAXM > 0 ? MAXM : 1];
+        uint32_t e[MAXM > 0 ? MAXM : 1];
+        uint32_t rr[MAXM + 1]; // rr[k]: remainder after a[0..k-1]; constant past M
+        rr[0] = P.n;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            if (k < (int)M) {
+                a[k] = uni(b0[k]);
+                rr[k + 1] = rr[k] - a[k] * P.g[k];
+            } else {
+                a[k] = 0;
+                rr[k + 1] = rr[k];
+            }
+        }
+        int32_t xs = (int32_t)uni(b0[M]);
+        const bool end_open = uni(b1[0]) == FZK_SENTINEL;
+        int32_t xe = 0;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) e[k] = 0;
+        if (!end_open) {
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k)
+                if (k < (int)M) e[k] = uni(b1[k]);
+            xe = (int32_t)uni(b1[M]);
+        }
+        uint32_t plen = 0;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) plen += a[k];
+        bool done = false;
+        while (!done) {
+            const uint32_t Rp = rr[MAXM];
+            const int32_t xhi = (int32_t)fdiv(Rp, P.div_G2);
+            bool last = !end_open;
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) last = last && (k >= (int)M || a[k] == e[k]);
+            const int32_t xlast = last ? xe - 1 : xhi;
+            ++n_rows;
+            if constexpr (MODE == FZM_EXISTS) {
+                const uint32_t f =
+                    __hip_atomic_load(io.found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (uni(f)) break;
+            }
+            for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
+                const uint32_t Rc = Rp - (uint32_t)c * P.G2;
+                const uint32_t Qc = fdiv(Rc, P.div_B);
+                const uint32_t Pc = Rc - Qc * P.B;
+                const bool active = (int32_t)lane <= xlast - c;
+                const uint32_t rho2 = Pc + lr2;
+                const int32_t q2 = (int32_t)(Qc - lq1);
+                const uint32_t ti = active ? rho2 : 0u;
+                const int2 ent = TLDS ? io.ltab[ti] : io.gtab[ti];
+                // a lane with no element starts at -1, so that the common
+                // decrement stays above -(n + 2 A) > -2^31 for every lane
+                int32_t ad0 = q2 - ent.y;
+                ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                lane_pref += active ? 1u : 0u;
+                uint32_t cnt = 0;
+                if constexpr (MODE == FZM_COUNT) {
+                    // two candidate steps per trip; the trip test is the
+                    // first step's own validity test
+                    int32_t ad = ad0;
+                    for (;;) {
+                        const bool c0 = ad >= 0;
+                        if (!__ballot(c0)) break;
+                        const bool c1 = ad >= delta;
+                        cnt += c0 ? 1u : 0u;
+                        cnt += c1 ? 1u : 0u;
+                        ad -= 2 * delta;
+                    }
+                    lane_el += cnt;
+                } else if constexpr (MODE == FZM_HIST) {
+                    // The lane's elements are counted one by one as in the
+                    // count consumer; their lengths step by len_step, so the
+                    // run is then recorded as a strided difference (finalize
+                    // integrates along the stride).
+                    int32_t ad = ad0;
+                    for (;;) {
+                        const bool c0 = ad >= 0;
+                        if (!__ballot(c0)) break;
+                        const bool c1 = ad >= delta;
+                        cnt += c0 ? 1u : 0u;
+                        cnt += c1 ? 1u : 0u;
+                        ad -= 2 * delta;
+                    }
+                    lane_el += cnt;
+                    if (cnt) {
+                        const uint32_t len0 =
+                            plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
+                        hist_run(P, io, len0, cnt, (int32_t)len_step);
+                    }
+                } else if constexpr (MODE == FZM_EXISTS) {
+                    // each element's length is compared with the target; the
+                    // wave looks at the lanes' verdicts once per chunk
+                    int32_t ad = ad0;
+                    uint32_t len = plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
+                    bool hit = false;
+                    for (;;) {
+                        const bool c0 = ad >= 0;
+                        if (!__ballot(c0)) break;
+                        const bool c1 = ad >= delta;
+                        cnt += c0 ? 1u : 0u;
+                        cnt += c1 ? 1u : 0u;
+                        hit = hit || (c0 && len == target) || (c1 && len + len_step == target);
+                        ad -= 2 * delta;
+                        len += 2 * len_step;
+                    }
+                    lane_el += cnt;
+                    if (__ballot(hit)) {
+                        __hip_atomic_store(io.found, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        done = true;
+                        break;
+                    }
+                } else { // FZM_STORE
+                    uint64_t L = 0;
+                    if (ad0 >= 0) L = fdiv((uint32_t)ad0, P.div_delta) + 1;
+                    const uint64_t incl = wave_incl_scan64(L, lane);
+                    const uint64_t T = readlane64(incl, FZK_WAVE - 1);
+                    io.s_incl[lane] = incl;
+                    io.s_t0[lane] = (uint32_t)ent.x;
+                    io.s_ad0[lane] = (uint32_t)ad0;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    // Rows are produced 64 at a time (lane = position in the
+                    // chunk's output), staged in LDS as one contiguous block
+                    // and written out as consecutive dwords: every store
+                    // instruction covers 256 bytes.
+                    const uint64_t lim = P.max_tuples;
+                    const uint32_t du = P.d_user;
+                    for (uint64_t p0 = 0; p0 < T && rank + p0 < lim; p0 += FZK_WAVE) {
+                        const uint64_t left = T - p0 < lim - rank - p0 ? T - p0 : lim - rank - p0;
+                        const uint32_t nb = left < FZK_WAVE ? (uint32_t)left : FZK_WAVE;
+                        const uint64_t p = p0 + lane;
+                        if (lane < nb) {
+                            uint32_t j = 0;
+#pragma unroll
+                            for (uint32_t st = FZK_WAVE / 2; st >= 1; st >>= 1)
+                                if (io.s_incl[j + st - 1] <= p) j += st;
+                            const uint32_t k = (uint32_t)(p - (j ? io.s_incl[j - 1] : 0ull));
+                            // coordinates a[0..M-1], x, t, ad; the first pad
+                            // (virtual) coordinates are not output
+                            uint32_t *st_row = io.s_stage + lane * du;
+#pragma unroll
+                            for (int q = 0; q < MAXM; ++q)
+                                if (q < (int)M && (uint32_t)q >= P.pad) st_row[q - P.pad] = a[q];
+                            if (M >= P.pad) st_row[M - P.pad] = (uint32_t)c + j;
+                            if (M + 1 >= P.pad) st_row[M + 1 - P.pad] = io.s_t0[j] + k * P.ord;
+                            st_row[M + 2 - P.pad] = io.s_ad0[j] - k * P.delta;
+                        }
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        uint32_t *dst = io.out + (rank + p0) * du;
+                        const uint32_t words = nb * du;
+                        for (uint32_t i = lane; i < words; i += FZK_WAVE) dst[i] = io.s_stage[i];
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    if (rank < lim) n_el += (T < lim - rank) ? T : (lim - rank);
+                    rank += T;
+                    if (rank >= lim) {
+                        done = true;
+                        break;
+                    }
+                }
+            }
+            if (done || last) break;
+            // next row: rightmost k < M whose a[k] can grow, deeper coordinates reset
+            int kk = -1;
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k)
+                if (k < (int)M && rr[k + 1] >= P.g[k]) kk = k;
+            if (kk < 0) break;
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) {
+                if (k == kk) {
+                    a[k] += 1;
+                    rr[k + 1] -= P.g[k];
+                } else if (k > kk) {
+                    a[k] = 0;
+                    rr[k + 1] = rr[k];
+                }
+            }
+            plen = 0;
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) plen += a[k];
+            xs = 0;
+        }
+    }
+    WalkOut o;
+    o.elements = MODE == FZM_STORE ? n_el : wave_sum64(lane_el);
+    o.rows = n_rows;
+    o.prefixes = wave_sum64(lane_pref);
+    return o;
+}
+
+// Single query.  Persistent workgroups of four waves; each wave takes slices
+// from an atomic cursor.
+// LDS: [residue table, 2B int2, when it fits][per-wave consumer scratch].
 template <int M, int MODE, bool TLDS>
 __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
 {
@@ -346,12 +636,18 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         for (uint32_t i = threadIdx.x; i < 2 * P.B; i += blockDim.x) ltab[i] = Bf.restab[i];
         scratch = lds + 2 * (((2 * P.B) + 1) & ~1u); // keep 16-byte alignment
     }
-    uint32_t *wbins = nullptr;
+    WalkIO io;
+    io.ltab = ltab;
+    io.gtab = Bf.restab;
+    io.wbins = nullptr;
+    io.gbins = Bf.hist;
+    io.found = &Bf.ctl->found;
+    io.out = Bf.out;
     uint64_t *grow = nullptr;
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) {
-            wbins = scratch + wave * (P.nbins + FZK_WAVE);
-            for (uint32_t i = lane; i < P.nbins + FZK_WAVE; i += FZK_WAVE) wbins[i] = 0;
+            io.wbins = (uint64_t *)(scratch + wave * 2 * P.nbins);
+            for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) io.wbins[i] = 0;
             grow = Bf.hist_rows + (uint64_t)blockIdx.x * P.nbins;
             for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = 0;
         }
@@ -359,21 +655,11 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     // store scratch per wave: scan (64 x u64), t0 and ad0 (64 x u32 each),
     // then the staging block of 64 rows x d_user words
     const uint32_t store_words = 4 * FZK_WAVE + FZK_WAVE * P.d_user;
-    uint64_t *s_incl = (uint64_t *)(scratch + wave * store_words);
-    uint32_t *s_t0 = (uint32_t *)(s_incl + FZK_WAVE);
-    uint32_t *s_ad0 = s_t0 + FZK_WAVE;
-    uint32_t *s_stage = s_ad0 + FZK_WAVE;
+    io.s_incl = (uint64_t *)(scratch + wave * store_words);
+    io.s_t0 = (uint32_t *)(io.s_incl + FZK_WAVE);
+    io.s_ad0 = io.s_t0 + FZK_WAVE;
+    io.s_stage = io.s_ad0 + FZK_WAVE;
     __syncthreads();
-
-    // lane * G2 = lq * B + lr (exact whenever the lane is active).  A lane
-    // reads the doubled residue table at rho' = Pc + (B - lr) with quotient
-    // q' = Qc - (lq + 1): no borrow to propagate.
-    const uint64_t lg = (uint64_t)lane * P.G2;
-    const uint32_t lq1 = (uint32_t)(lg / P.B) + 1;
-    const uint32_t lr2 = P.B - (uint32_t)(lg % P.B);
-    const uint32_t len_step = P.ord - P.delta;
-    const int32_t delta = (int32_t)P.delta;
-    uint64_t hist_since_flush = 0;
 
     // The spine of this loop must stay free of lane-dependent branches: every
     // lane takes part in the cursor atomic (only lane 0 adds 1) and every lane
@@ -389,233 +675,37 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         }
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
-        const uint32_t *b1 = b0 + NP;
-        // per-lane element counters: a chunk adds at most n + 1 per lane to
-        // the 32-bit counter, which is folded into the 64-bit one per chunk
-        uint64_t lane_el = 0;
-        uint32_t lane_pref = 0;
-        uint64_t n_el = 0, n_rows = 0;
-        if (uni(b0[0]) != FZK_SENTINEL) {
-            uint32_t a[M > 0 ? M : 1];
-            uint32_t e[M > 0 ? M : 1];
-            uint32_t rr[M + 1]; // rr[k]: remainder after a[0..k-1]
-            rr[0] = P.n;
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                a[k] = uni(b0[k]);
-                rr[k + 1] = rr[k] - a[k] * P.g[k];
-            }
-            int32_t xs = (int32_t)uni(b0[M]);
-            const bool end_open = uni(b1[0]) == FZK_SENTINEL;
-            int32_t xe = 0;
-#pragma unroll
-            for (int k = 0; k < M; ++k) e[k] = 0;
-            if (!end_open) {
-#pragma unroll
-                for (int k = 0; k < M; ++k) e[k] = uni(b1[k]);
-                xe = (int32_t)uni(b1[M]);
-            }
-            uint32_t plen = 0;
-#pragma unroll
-            for (int k = 0; k < M; ++k) plen += a[k];
-            uint64_t rank = Bf.base[s];
-            bool done = false;
-            while (!done) {
-                const uint32_t Rp = rr[M];
-                const int32_t xhi = (int32_t)fdiv(Rp, P.div_G2);
-                bool last = !end_open;
-#pragma unroll
-                for (int k = 0; k < M; ++k) last = last && (a[k] == e[k]);
-                const int32_t xlast = last ? xe - 1 : xhi;
-                ++n_rows;
-                if constexpr (MODE == FZM_EXISTS) {
-                    const uint32_t f = __hip_atomic_load(&Bf.ctl->found, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-                    if (uni(f)) break;
-                }
-                for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
-                    const uint32_t Rc = Rp - (uint32_t)c * P.G2;
-                    const uint32_t Qc = fdiv(Rc, P.div_B);
-                    const uint32_t Pc = Rc - Qc * P.B;
-                    const bool active = (int32_t)lane <= xlast - c;
-                    const uint32_t rho2 = Pc + lr2;
-                    const int32_t q2 = (int32_t)(Qc - lq1);
-                    const uint32_t ti = active ? rho2 : 0u;
-                    const int2 ent = TLDS ? ltab[ti] : Bf.restab[ti];
-                    // a lane with no element starts at -1, so that the common
-                    // decrement stays above -(n + 2 A) > -2^31 for every lane
-                    int32_t ad0 = q2 - ent.y;
-                    ad0 = (active && ad0 >= 0) ? ad0 : -1;
-                    lane_pref += active ? 1u : 0u;
-                    uint32_t cnt = 0;
-                    if constexpr (MODE == FZM_COUNT) {
-                        // two candidate steps per trip; the trip test is the
-                        // first step's own validity test
-                        int32_t ad = ad0;
-                        for (;;) {
-                            const bool c0 = ad >= 0;
-                            if (!__ballot(c0)) break;
-                            const bool c1 = ad >= delta;
-                            cnt += c0 ? 1u : 0u;
-                            cnt += c1 ? 1u : 0u;
-                            ad -= 2 * delta;
-                        }
-                        lane_el += cnt;
-                    } else if constexpr (MODE == FZM_HIST) {
-                        int32_t ad = ad0;
-                        uint32_t len = plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
-                        uint64_t *gh = Bf.hist;
-                        // lanes without an element add into a private spare bin
-                        const uint32_t spare = P.nbins + lane;
-                        for (;;) {
-                            const bool c0 = ad >= 0;
-                            if (!__ballot(c0)) break;
-                            cnt += c0 ? 1u : 0u;
-                            if (P.hist_in_lds) {
-                                atomicAdd(&wbins[c0 ? len : spare], 1u);
-                            } else if (c0) {
-                                atomicAdd((unsigned long long *)&gh[len], 1ull);
-                            }
-                            ad -= delta;
-                            len += len_step;
-                        }
-                        lane_el += cnt;
-                    } else if constexpr (MODE == FZM_EXISTS) {
-                        int32_t ad = ad0;
-                        uint32_t len = plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
-                        bool hit = false;
-                        for (;;) {
-                            const bool c0 = ad >= 0;
-                            if (!__ballot(c0)) break;
-                            cnt += c0 ? 1u : 0u;
-                            if (__ballot(c0 && (uint64_t)len == P.target_len)) {
-                                hit = true;
-                                break;
-                            }
-                            ad -= delta;
-                            len += len_step;
-                        }
-                        lane_el += cnt;
-                        if (hit) {
-                            __hip_atomic_store(&Bf.ctl->found, 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-                            done = true;
-                            break;
-                        }
-                    } else { // FZM_STORE
-                        uint64_t L = 0;
-                        if (ad0 >= 0) L = fdiv((uint32_t)ad0, P.div_delta) + 1;
-                        const uint64_t incl = wave_incl_scan64(L, lane);
-                        const uint64_t T = readlane64(incl, FZK_WAVE - 1);
-                        s_incl[lane] = incl;
-                        s_t0[lane] = (uint32_t)ent.x;
-                        s_ad0[lane] = (uint32_t)ad0;
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        // Rows are produced 64 at a time (lane = position in
-                        // the chunk's output), staged in LDS as one
-                        // contiguous block and written out as consecutive
-                        // dwords: every store instruction covers 256 bytes.
-                        const uint64_t lim = P.max_tuples;
-                        const uint32_t du = P.d_user;
-                        for (uint64_t p0 = 0; p0 < T && rank + p0 < lim; p0 += FZK_WAVE) {
-                            const uint64_t left = T - p0 < lim - rank - p0 ? T - p0 : lim - rank - p0;
-                            const uint32_t nb = left < FZK_WAVE ? (uint32_t)left : FZK_WAVE;
-                            const uint64_t p = p0 + lane;
-                            if (lane < nb) {
-                                uint32_t j = 0;
-#pragma unroll
-                                for (uint32_t st = FZK_WAVE / 2; st >= 1; st >>= 1)
-                                    if (s_incl[j + st - 1] <= p) j += st;
-                                const uint32_t k = (uint32_t)(p - (j ? s_incl[j - 1] : 0ull));
-                                uint32_t v[M + 3];
-#pragma unroll
-                                for (int q = 0; q < M; ++q) v[q] = a[q];
-                                v[M] = (uint32_t)c + j;
-                                v[M + 1] = s_t0[j] + k * P.ord;
-                                v[M + 2] = s_ad0[j] - k * P.delta;
-                                uint32_t *st_row = s_stage + lane * du - P.pad;
-#pragma unroll
-                                for (int q = 0; q < M + 3; ++q)
-                                    if ((uint32_t)q >= P.pad) st_row[q] = v[q];
-                            }
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                            __builtin_amdgcn_wave_barrier();
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                            uint32_t *dst = Bf.out + (rank + p0) * du;
-                            const uint32_t words = nb * du;
-                            for (uint32_t i = lane; i < words; i += FZK_WAVE) dst[i] = s_stage[i];
-                            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                            __builtin_amdgcn_wave_barrier();
-                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        if (rank < lim) n_el += (T < lim - rank) ? T : (lim - rank);
-                        rank += T;
-                        if (rank >= lim) {
-                            done = true;
-                            break;
-                        }
-                    }
-                }
-                if (done || last) break;
-                // next row: rightmost k whose a[k] can grow, deeper coordinates reset
-                int kk = -1;
-#pragma unroll
-                for (int k = 0; k < M; ++k)
-                    if (rr[k + 1] >= P.g[k]) kk = k;
-                if (kk < 0) break;
-#pragma unroll
-                for (int k = 0; k < M; ++k) {
-                    if (k == kk) {
-                        a[k] += 1;
-                        rr[k + 1] -= P.g[k];
-                    } else if (k > kk) {
-                        a[k] = 0;
-                        rr[k + 1] = rr[k];
-                    }
-                }
-                plen = 0;
-#pragma unroll
-                for (int k = 0; k < M; ++k) plen += a[k];
-                xs = 0;
-            }
-        }
-        if constexpr (MODE != FZM_STORE) n_el = wave_sum64(lane_el);
+        const WalkOut o = walk_slice<M, MODE, TLDS>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
         {
             FzSliceRec rec;
-            rec.elements = n_el;
-            rec.rows = n_rows;
-            rec.prefixes = wave_sum64(lane_pref);
+            rec.elements = o.elements;
+            rec.rows = o.rows;
+            rec.prefixes = o.prefixes;
             rec.t_begin = t_begin;
             rec.t_end = wall_clock64();
             Bf.recs[s] = rec; // the same value from every lane
-        }
-        if constexpr (MODE == FZM_HIST) {
-            hist_since_flush += n_el;
-            if (P.hist_in_lds && hist_since_flush > (1ull << 31)) {
-                for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
-                    const uint32_t h = wbins[i];
-                    if (h) {
-                        atomicAdd((unsigned long long *)&grow[i], (unsigned long long)h);
-                        wbins[i] = 0;
-                    }
-                }
-                hist_since_flush = 0;
-            }
         }
     }
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) {
             for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
-                const uint32_t h = wbins[i];
+                const uint64_t h = io.wbins[i];
                 if (h) atomicAdd((unsigned long long *)&grow[i], (unsigned long long)h);
             }
         }
     }
+}
+
+// The histogram consumer leaves a strided difference array (stride
+// |ord - delta|, the change of length between consecutive elements of a
+// run); running sums along each residue chain turn it into the histogram.
+// Stride 0: the bins already are the histogram.  Whole workgroup.
+__device__ void integrate_hist(const FzPlan &P, uint64_t *h, uint64_t *part)
+{
+    const int32_t step = (int32_t)(P.ord - P.delta);
+    const uint32_t mag = step < 0 ? (uint32_t)-step : (uint32_t)step;
+    if (mag == 0 || mag >= P.nbins) return;
+    chain_scan<false>(h, P.nbins, mag, [&](uint32_t v) { return h[v]; }, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -626,6 +716,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
 __global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf, uint32_t nwg)
 {
     __shared__ uint64_t red[4][1024 / FZK_WAVE];
+    __shared__ uint64_t part[1024];
     const uint32_t tid = threadIdx.x, lane = tid % FZK_WAVE, w = tid / FZK_WAVE;
     const uint32_t nw = blockDim.x / FZK_WAVE;
     uint64_t el = 0, rows = 0, pref = 0, bad = 0;
@@ -638,20 +729,20 @@ __global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf, 
     }
     uint64_t lo = ~0ull, hi = 0;
     if (P.mode == FZM_HIST) {
-        for (uint32_t l = tid; l < P.nbins; l += blockDim.x) {
-            uint64_t h;
-            if (P.hist_in_lds) {
-                h = 0;
+        if (P.hist_in_lds) {
+            for (uint32_t l = tid; l < P.nbins; l += blockDim.x) {
+                uint64_t h = 0;
                 for (uint32_t b = 0; b < nwg; ++b) h += Bf.hist_rows[(uint64_t)b * P.nbins + l];
                 Bf.hist[l] = h;
-            } else {
-                h = Bf.hist[l];
             }
-            if (h) {
+            __syncthreads();
+        }
+        integrate_hist(P, Bf.hist, part);
+        for (uint32_t l = tid; l < P.nbins; l += blockDim.x)
+            if (Bf.hist[l]) {
                 lo = l < lo ? l : lo;
                 hi = l > hi ? l : hi;
             }
-        }
     }
     for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
         el += __shfl_xor(el, o);
@@ -718,6 +809,203 @@ __global__ void fz_unrank_kernel(FzPlan P, FzBufs Bf, const uint64_t *ranks, uin
     dst[P.d - 1] = v / P.B;
 }
 
+// ---------------------------------------------------------------------------
+// Batches.  One launch per step for all queries: count and work tables of the
+// sliced queries (one workgroup each), residue tables, slice bounds (one
+// thread per boundary), the walker (persistent, work items taken from one
+// cursor across all queries: a wave that finishes a slice of one query takes
+// the next item, whatever its query), and a per-query finalize.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) fz_batch_dp_kernel(FzBatchBufs B, const uint32_t *ids)
+{
+    __shared__ uint64_t part[1024];
+    const FzBatchQuery &Q = B.queries[ids[blockIdx.x]];
+    const FzPlan P = Q.plan;
+    dp_query(P, B.tables + Q.s_off, B.tables + Q.c_off, part);
+}
+
+__global__ void fz_batch_restab_kernel(FzBatchBufs B)
+{
+    const FzBatchQuery &Q = B.queries[blockIdx.x];
+    const FzPlan P = Q.plan;
+    if (P.d == 0) return; // rejected query
+    for (uint32_t i = threadIdx.x; i < 2 * P.B; i += blockDim.x)
+        B.restabs[Q.tab_off + i] = restab_entry(P, i);
+}
+
+// One thread per boundary job.  Queries that are not sliced have one slice,
+// from the prefix (0,...,0) to the end of the set.
+__global__ void fz_batch_slices_kernel(FzBatchBufs B)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) *B.cursor = 0;
+    if (t >= B.n_bjobs) return;
+    const FzBatchJob job = B.bjobs[t];
+    const FzBatchQuery &Q = B.queries[job.q];
+    const FzPlan P = Q.plan;
+    const uint32_t bi = Q.bound_off + job.j;
+    uint32_t *out = B.bounds + (uint64_t)bi * B.bstride;
+    if (!Q.sliced) {
+        if (job.j == 0) {
+            for (uint32_t k = 0; k + 2 < P.d; ++k) out[k] = 0;
+            B.base[bi] = 0;
+        } else {
+            out[0] = FZK_SENTINEL;
+            B.base[bi] = ~0ull;
+        }
+        return;
+    }
+    const uint64_t *S = B.tables + Q.s_off;
+    const uint64_t *C = B.tables + Q.c_off;
+    if (job.j == 0) {
+        const uint64_t N = S[P.n];
+        B.res[job.q].total = N;
+        if (N == ~0ull || C[P.n] == ~0ull) B.res[job.q].status = FZS_OVERFLOW;
+    }
+    B.base[bi] = slice_bound(P, S, C, Q.n_slices, job.j, out);
+}
+
+template <int MAXM>
+__global__ void __launch_bounds__(FZK_WG)
+    fz_batch_enum_kernel(FzBatchBufs B, uint32_t lds_bins, uint32_t max_du)
+{
+    extern __shared__ __align__(16) uint32_t lds[];
+    const uint32_t lane = __lane_id();
+    const uint32_t wave = threadIdx.x / FZK_WAVE;
+    // per-wave LDS: store scratch (scan, t0, ad0, 64 rows), then 64-bit
+    // histogram bins
+    const uint32_t store_words = max_du ? 4 * FZK_WAVE + FZK_WAVE * max_du : 0;
+    const uint32_t bin_words = 2 * lds_bins;
+    uint32_t *mine = lds + wave * ((store_words + bin_words + 3) & ~3u);
+    WalkIO io;
+    io.ltab = nullptr;
+    io.s_incl = (uint64_t *)mine;
+    io.s_t0 = (uint32_t *)(io.s_incl + FZK_WAVE);
+    io.s_ad0 = io.s_t0 + FZK_WAVE;
+    io.s_stage = io.s_ad0 + FZK_WAVE;
+    uint64_t *wb = (uint64_t *)(mine + store_words);
+
+    // uniform spine, as in the single-query walker
+    for (;;) {
+        const uint32_t old = atomicAdd(B.cursor, lane == 0 ? 1u : 0u);
+        const uint32_t it = __builtin_amdgcn_readlane(old, 0);
+        if (it >= B.n_items) break;
+        const uint64_t t_begin = wall_clock64();
+        const uint32_t q = uni(B.items[it].q);
+        const uint32_t s = uni(B.items[it].j);
+        const FzBatchQuery &Q = B.queries[q];
+        const FzPlan P = Q.plan;
+        const uint32_t M = uni(P.d) - 3;
+        const uint32_t mode = uni(P.mode);
+        WalkOut o;
+        o.elements = o.rows = o.prefixes = 0;
+        bool skip = false;
+        if (mode == FZM_EXISTS) {
+            const uint32_t f =
+                __hip_atomic_load(&B.res[q].found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            skip = uni(f) != 0;
+        }
+        if (!skip) {
+            const uint32_t bi = Q.bound_off + s;
+            const uint32_t *b0 = B.bounds + (uint64_t)bi * B.bstride;
+            const uint32_t *b1 = b0 + B.bstride;
+            const uint64_t base = B.base[bi];
+            io.gtab = B.restabs + Q.tab_off;
+            io.found = &B.res[q].found;
+            io.gbins = B.bins + Q.bins_off;
+            io.out = Q.out;
+            io.wbins = nullptr;
+            const bool lds_hist = mode == FZM_HIST && P.hist_in_lds;
+            if (lds_hist) {
+                io.wbins = wb;
+                for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) wb[i] = 0;
+            }
+            if (mode == FZM_COUNT)
+                o = walk_slice<MAXM, FZM_COUNT, false>(P, M, b0, b1, base, io, lane);
+            else if (mode == FZM_HIST)
+                o = walk_slice<MAXM, FZM_HIST, false>(P, M, b0, b1, base, io, lane);
+            else if (mode == FZM_EXISTS)
+                o = walk_slice<MAXM, FZM_EXISTS, false>(P, M, b0, b1, base, io, lane);
+            else
+                o = walk_slice<MAXM, FZM_STORE, false>(P, M, b0, b1, base, io, lane);
+            if (lds_hist) {
+                for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
+                    const uint64_t h = wb[i];
+                    if (h) atomicAdd((unsigned long long *)&io.gbins[i], (unsigned long long)h);
+                }
+            }
+        }
+        FzSliceRec rec;
+        rec.elements = o.elements;
+        rec.rows = o.rows;
+        rec.prefixes = o.prefixes;
+        rec.t_begin = t_begin;
+        rec.t_end = wall_clock64();
+        B.recs[it] = rec; // the same value from every lane
+    }
+}
+
+// One workgroup per query: element total and the slice self-check (sliced
+// queries), the histogram's integration and min / max length, rows written
+// (stores).
+__global__ void __launch_bounds__(FZK_WG) fz_batch_finalize_kernel(FzBatchBufs B)
+{
+    __shared__ uint64_t part[FZK_WG];
+    __shared__ uint64_t red[4][FZK_WG / FZK_WAVE];
+    const uint32_t tid = threadIdx.x, lane = tid % FZK_WAVE, w = tid / FZK_WAVE;
+    const uint32_t q = blockIdx.x;
+    const FzBatchQuery &Q = B.queries[q];
+    const FzPlan P = Q.plan;
+    FzBatchResult &R = B.res[q];
+    if (P.d == 0) return; // rejected query: the whole workgroup leaves
+    uint64_t el = 0, bad = 0;
+    for (uint32_t s = tid; s < Q.n_slices; s += FZK_WG) {
+        const uint64_t e = B.recs[Q.item_off + s].elements;
+        el += e;
+        if (Q.sliced && P.mode != FZM_EXISTS) {
+            const uint64_t want = B.base[Q.bound_off + s + 1] - B.base[Q.bound_off + s];
+            if (e != want) bad = 1;
+        }
+    }
+    uint64_t lo = ~0ull, hi = 0;
+    if (P.mode == FZM_HIST) {
+        uint64_t *bins = B.bins + Q.bins_off;
+        integrate_hist(P, bins, part);
+        for (uint32_t l = tid; l < P.nbins; l += FZK_WG)
+            if (bins[l]) {
+                lo = l < lo ? l : lo;
+                hi = l > hi ? l : hi;
+            }
+    }
+    for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
+        el += __shfl_xor(el, o);
+        bad |= __shfl_xor(bad, o);
+        const uint64_t lo2 = __shfl_xor(lo, o), hi2 = __shfl_xor(hi, o);
+        lo = lo2 < lo ? lo2 : lo;
+        hi = hi2 > hi ? hi2 : hi;
+    }
+    if (lane == 0) {
+        red[0][w] = el;
+        red[1][w] = bad;
+        red[2][w] = lo;
+        red[3][w] = hi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (uint32_t i = 1; i < FZK_WG / FZK_WAVE; ++i) {
+            el += red[0][i];
+            bad |= red[1][i];
+            lo = red[2][i] < lo ? red[2][i] : lo;
+            hi = red[3][i] > hi ? red[3][i] : hi;
+        }
+        R.count = el;
+        if (bad) R.status |= FZS_MISMATCH;
+        R.min_len = lo;
+        R.max_len = hi;
+        R.written = P.mode == FZM_STORE ? el : 0;
+    }
+}
+
 __global__ void fz_zero_kernel(uint64_t *p, uint64_t count)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -755,7 +1043,7 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
     const uint32_t waves = FZK_WG / FZK_WAVE;
     size_t bytes = p.restab_in_lds ? (size_t)2 * ((2 * p.B + 1) & ~1u) * sizeof(uint32_t) : 0;
     if (p.mode == FZM_HIST && p.hist_in_lds)
-        bytes += (size_t)waves * (p.nbins + FZK_WAVE) * sizeof(uint32_t);
+        bytes += (size_t)waves * p.nbins * sizeof(uint64_t);
     if (p.mode == FZM_STORE)
         bytes += (size_t)waves * (4 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
     return bytes;
@@ -827,5 +1115,44 @@ hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *r
     const uint64_t blocks = (nranks + 255) / 256;
     hipLaunchKernelGGL(fz_unrank_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, p, b, ranks,
                        nranks, out);
+    return hipGetLastError();
+}
+
+template <int MAXM>
+static void launch_batch_enum(const FzBatchBufs &b, uint32_t nwg, uint32_t lds_bins,
+                              uint32_t max_du, hipStream_t s)
+{
+    const uint32_t store_words = max_du ? 4 * FZK_WAVE + FZK_WAVE * max_du : 0;
+    const uint32_t bin_words = 2 * lds_bins;
+    const size_t lds = (size_t)(FZK_WG / FZK_WAVE) * ((store_words + bin_words + 3) & ~3u) * 4;
+    hipLaunchKernelGGL((fz_batch_enum_kernel<MAXM>), dim3(nwg), dim3(FZK_WG), lds, s, b,
+                       lds_bins, max_du);
+}
+
+hipError_t fzk_launch_batch_prep(const FzBatchBufs &b, uint32_t n_sliced,
+                                 const uint32_t *sliced_ids, hipStream_t s)
+{
+    hipLaunchKernelGGL(fz_zero_kernel, dim3(64), dim3(256), 0, s, (uint64_t *)b.res,
+                       (uint64_t)b.nq * (sizeof(FzBatchResult) / 8));
+    if (b.n_bins)
+        hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.bins, b.n_bins);
+    if (n_sliced)
+        hipLaunchKernelGGL(fz_batch_dp_kernel, dim3(n_sliced), dim3(1024), 0, s, b, sliced_ids);
+    hipLaunchKernelGGL(fz_batch_restab_kernel, dim3(b.nq), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(fz_batch_slices_kernel, dim3((b.n_bjobs + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t fzk_launch_batch_walk(const FzBatchBufs &b, uint32_t maxm, uint32_t nwg,
+                                 uint32_t lds_bins, uint32_t max_du, hipStream_t s)
+{
+    if (maxm <= 5) launch_batch_enum<5>(b, nwg, lds_bins, max_du, s);
+    else launch_batch_enum<13>(b, nwg, lds_bins, max_du, s);
+    return hipGetLastError();
+}
+
+hipError_t fzk_launch_batch_finalize(const FzBatchBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(fz_batch_finalize_kernel, dim3(b.nq), dim3(FZK_WG), 0, s, b);
     return hipGetLastError();
 }

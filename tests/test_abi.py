@@ -74,3 +74,18 @@ def test_no_device_is_a_clean_error():
     with pytest.raises(fz.FzError) as e:
         fz.count(100, [3, 5, 7])
     assert e.value.status == fz.FZ_EDEVICE
+
+
+def test_batch_validation_without_a_device():
+    L = fz._lib
+    assert L.fz_batch(None, None, 0, None) == fz.FZ_OK
+    r = (fz.fz_result * 1)()
+    q = (fz.fz_query * 1)()
+    assert L.fz_batch(None, r, 1, None) == fz.FZ_EINVAL
+    assert L.fz_batch(q, None, 1, None) == fz.FZ_EINVAL
+    assert fz.batch([]) == []
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(fz.FzError) as e:
+            fz.batch([dict(n=10, g=[3, 5], mode="count")])
+        assert e.value.status == fz.FZ_EDEVICE

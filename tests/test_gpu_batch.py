@@ -1,0 +1,188 @@
+"""GPU parity of batches (fz_batch): many queries, mixed consumers, one launch.
+
+Every query of a batch is checked against the CPU oracle (bit-exact), and a
+query's result must be the same alone (the single-query entry points) and in
+the mix.  The 4096-query workload (d in 3..8, generators in [5,1000], n
+log-uniform in [1e3,1e6], count / histogram / predicate) is checked in full
+against the oracle's generating-function counts, and its histograms and
+predicates against the oracle where the oracle's table fits (the rest by the
+properties that hold at any size: bins sum to |Z|; a predicate that found no
+witness visited all of Z).
+"""
+import random
+
+import numpy as np
+import pytest
+
+import fzinputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def fz():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible: the gpu tests need an MI355X")
+    import paper_2405_07989_amd as m
+    return m
+
+
+def tiny_queries(seed, count):
+    rng = random.Random(seed)
+    qs = []
+    while len(qs) < count:
+        d = rng.randint(1, 7)
+        g = [rng.randint(1, 15) for _ in range(d)]
+        n = rng.randint(0, 150 if d <= 3 else 70)
+        if oracle.dp_count(n, g) > 200_000:
+            continue
+        mode = rng.choice(["count", "hist", "exists", "store"])
+        q = dict(n=n, g=g, mode=mode)
+        if mode == "exists":
+            q["target_len"] = rng.randint(0, n // min(g) + 1)
+        qs.append(q)
+    return qs
+
+
+def check_against_oracle(q, r):
+    n, g = q["n"], q["g"]
+    assert r["status"] >= 0, (q, r)
+    if q["mode"] == "count":
+        assert r["count"] == oracle.count(n, g)
+    elif q["mode"] == "hist":
+        h, lo, hi = oracle.hist(n, g)
+        assert np.array_equal(r["bins"], h) and (r["min_len"], r["max_len"]) == (lo, hi)
+        assert r["count"] == int(h.sum())
+    elif q["mode"] == "exists":
+        assert r["found"] == oracle.exists(n, g, q["target_len"])
+    else:
+        want = oracle.store(n, g)
+        m = q.get("max_tuples", q["out"].shape[0])
+        got = q["out"][: r["written"]].cpu().numpy().view(np.uint32)
+        assert r["written"] == min(m, len(want)) and r["total"] == len(want)
+        assert np.array_equal(got, want[: r["written"]])
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_tiny_mixed_batch(fz, seed):
+    qs = tiny_queries(seed, 120)
+    for q in qs:
+        if q["mode"] == "store":
+            cnt = oracle.dp_count(q["n"], q["g"])
+            rows = max(cnt + random.Random(q["n"]).randint(-2, 2), 1)
+            q["out"] = torch.zeros((rows, len(q["g"])), dtype=torch.int32, device="cuda")
+    res = fz.batch(qs)
+    for q, r in zip(qs, res):
+        check_against_oracle(q, r)
+
+
+def test_invalid_queries_do_not_stop_the_batch(fz):
+    qs = [dict(n=100, g=[3, 5, 7], mode="count"),
+          dict(n=100, g=[3, 0, 7], mode="count"),          # g_i = 0
+          dict(n=2**31, g=[3, 5], mode="count"),          # too large
+          dict(n=50, g=[4, 6], mode="hist"),
+          dict(n=60, g=[5, 7, 2**24 + 1], mode="count"),   # last generator too large
+          dict(n=77, g=[2, 9, 11, 4], mode="exists", target_len=20)]
+    res = fz.batch(qs)
+    assert res[1]["status"] == fz.FZ_EINVAL
+    assert res[2]["status"] == fz.FZ_EOVERFLOW
+    assert res[4]["status"] == fz.FZ_E2BIG
+    for i in (0, 3, 5):
+        check_against_oracle(qs[i], res[i])
+
+
+def test_empty_batch(fz):
+    assert fz.batch([]) == []
+
+
+def test_store_queries_in_a_batch(fz):
+    qs = []
+    for n, g, m in [(10000, [11, 13, 17, 23], 3009519), (10000, [11, 13, 17, 23], 1000),
+                    (5000, [13, 37, 38, 40], 10**6), (3000, [13, 37, 38, 40, 41], 50000),
+                    (1, [2, 4], 5)]:
+        qs.append(dict(n=n, g=g, mode="store", max_tuples=m,
+                       out=torch.zeros((m, len(g)), dtype=torch.int32, device="cuda")))
+    qs.append(dict(n=10000, g=[11, 13, 17, 23], mode="count"))
+    res = fz.batch(qs)
+    for q, r in zip(qs, res):
+        check_against_oracle(q, r)
+    assert res[1]["status"] == fz.FZ_TRUNCATED
+
+
+@pytest.fixture(scope="module")
+def workload():
+    return fzinputs.load_golden()["batch"]["queries"]
+
+
+@pytest.fixture(scope="module")
+def batch_result(fz, workload):
+    qs = [dict(n=q["n"], g=q["g"], mode=q["mode"], target_len=q["target_len"]) for q in workload]
+    return qs, fz.batch(qs)
+
+
+def test_workload_counts(batch_result, workload):
+    qs, res = batch_result
+    for q, r, w in zip(qs, res, workload):
+        assert r["status"] == 0, (q, r)
+        if q["mode"] in ("count", "hist"):
+            assert r["count"] == w["count"], q
+        if q["mode"] == "hist":
+            assert int(r["bins"].sum()) == w["count"]
+        if q["mode"] == "exists" and not r["found"]:
+            assert r["count"] == w["count"], q  # no witness: all of Z was visited
+
+
+def test_workload_histograms_and_predicates(batch_result, workload):
+    qs, res = batch_result
+    checked_h = checked_e = 0
+    for q, r, w in zip(qs, res, workload):
+        nb = q["n"] // min(q["g"]) + 1
+        if (q["n"] + 1) * nb > 3_000_000:
+            continue
+        if q["mode"] == "hist":
+            assert np.array_equal(r["bins"], oracle.dp_hist(q["n"], q["g"])), q
+            checked_h += 1
+        elif q["mode"] == "exists":
+            t = q["target_len"]
+            want = t < nb and bool(oracle.dp_hist(q["n"], q["g"])[t] > 0)
+            assert r["found"] == want, q
+            checked_e += 1
+    assert checked_h > 200 and checked_e > 200
+
+
+def test_alone_equals_in_the_mix(fz, batch_result, workload):
+    qs, res = batch_result
+    rng = random.Random(4)
+    for i in rng.sample(range(len(qs)), 60):
+        q, r = qs[i], res[i]
+        if q["mode"] == "count":
+            assert fz.count(q["n"], q["g"]) == r["count"]
+        elif q["mode"] == "hist":
+            h, lo, hi = fz.length_hist(q["n"], q["g"])
+            assert np.array_equal(h, r["bins"]) and (lo, hi) == (r["min_len"], r["max_len"])
+        else:
+            assert fz.exists(q["n"], q["g"], q["target_len"]) == r["found"]
+
+
+def test_autotune_keeps_results(fz):
+    qs = [q for q in tiny_queries(5, 80) if q["mode"] != "store"]
+    before = fz.batch(qs)
+    try:
+        t = fz.autotune(qs, reps=1)
+        assert t["candidates"] == 15 and t["ms"] <= t["default_ms"]
+        assert t["slices_per_wave"] in (4, 8, 16, 32, 64) and t["workgroups_per_cu"] in (2, 4, 8)
+        after = fz.batch(qs)
+    finally:
+        fz.config_set("slices_per_wave", 0)
+        fz.config_set("workgroups_per_cu", 0)
+    for q, a, b in zip(qs, before, after):
+        assert a["status"] == b["status"] == 0 and a["found"] == b["found"], q
+        # a predicate that found a witness stops early: how many elements it
+        # visited first depends on the slicing
+        if not (q["mode"] == "exists" and a["found"]):
+            assert a["count"] == b["count"], q
+        if q["mode"] == "hist":
+            assert np.array_equal(a["bins"], b["bins"])
