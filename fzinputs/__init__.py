@@ -101,6 +101,27 @@ def draw_query(rng: SplitMix64) -> dict:
     return dict(n=n, g=g, mode=mode, target_len=n // max(g) + 1)
 
 
+STORE_SHARE = 0.2
+
+
+def draw_served(rng: SplitMix64) -> dict:
+    """One query of the served stream: drawn as draw_query, then made a store
+    query with probability STORE_SHARE (one more uniform draw)."""
+    q = draw_query(rng)
+    if rng.uniform01() < STORE_SHARE:
+        q["mode"] = "store"
+    return q
+
+
+def served_query(seed: int, redraws: int) -> dict:
+    """Query of the served stream with this seed, after the recorded number
+    of redraws (draws rejected for their size when the stream was fixed)."""
+    rng = SplitMix64(seed)
+    for _ in range(redraws + 1):
+        q = draw_served(rng)
+    return q
+
+
 def query_seed(master_seed: int, i: int) -> int:
     """Seed of query i: the i-th output of SplitMix64(master_seed)."""
     rng = SplitMix64(master_seed)
@@ -125,3 +146,10 @@ def load_golden() -> dict:
     """The stored choices and expected values (see module docstring)."""
     with open(GOLDEN) as f:
         return json.load(f)
+
+
+def served_stream(golden: dict | None = None) -> list[dict]:
+    """The served stream's queries, in arrival order, from the stored seeds."""
+    w = (golden or load_golden())["served"]
+    seeds = query_seeds(w["master_seed"], len(w["redraws"]))
+    return [served_query(s, k) for s, k in zip(seeds, w["redraws"])]

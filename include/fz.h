@@ -160,6 +160,47 @@ typedef struct {
  * for NULL arrays. */
 int fz_batch(const fz_query *q, fz_result *r, uint32_t nq, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving.  A server takes queries one at a time from any thread
+ * (fz_submit) and hands each result to fz_wait.  Its own thread keeps up to
+ * max_inflight batches on the device, each on its own stream: whatever has
+ * arrived is launched as one batch as soon as a launch slot is free, so
+ * queries that arrive while others run start without waiting for them, and
+ * the batches overlap on the GPU.  A query's result is ready as soon as its
+ * own last slice is done, whatever the rest of its batch is doing.
+ * Admission: a query whose count/work tables, residue table and bins would
+ * exceed mem_budget, or a store query whose count table says |Z| >
+ * max_store_tuples, finishes with FZ_E2BIG (a refused store query reports
+ * |Z| in total).  Results are the same as alone (fz_batch, or the
+ * single-query entry points).
+ * The server uses the device current at fz_server_create.  fz_submit copies
+ * q and its generators; q->bins (host) and q->d_out (device) must stay valid
+ * until fz_wait has returned that ticket's result.  Every ticket must be
+ * collected with fz_wait exactly once; FZ_EINVAL for an unknown ticket.
+ * fz_server_destroy finishes the queries already submitted, then frees the
+ * server (results not yet collected are dropped).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t max_inflight;     /* launch slots (streams), 1..8; 0: 2 */
+    uint32_t max_batch;        /* queries per launch, 1..65536; 0: 4096 */
+    uint64_t mem_budget;       /* device bytes of tables per launch; 0: 8 GiB */
+    uint64_t max_store_tuples; /* admission cap of a store query; 0: 10^7 */
+} fz_server_cfg;
+
+typedef struct fz_server fz_server;
+
+typedef struct {
+    uint64_t submitted, completed, launches;
+    double mean_batch;         /* queries per launch */
+    double p50_us, p99_us, max_us, mean_us; /* fz_submit to result ready */
+} fz_server_stats;
+
+int fz_server_create(const fz_server_cfg *cfg, fz_server **out); /* cfg may be NULL */
+int fz_submit(fz_server *s, const fz_query *q, uint64_t *ticket);
+int fz_wait(fz_server *s, uint64_t ticket, fz_result *r); /* blocks */
+int fz_server_stats_read(fz_server *s, fz_server_stats *out, int reset);
+int fz_server_destroy(fz_server *s);
+
 /* Work statistics of the last successful enumeration on this device:
  * slices used, rows walked (one row = one prefix a_1..a_{d-3}), prefixes
  * (a_1..a_{d-2}) visited by lanes, candidate steps taken (one per element

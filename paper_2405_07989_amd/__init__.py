@@ -75,6 +75,18 @@ class fz_tune_result(ctypes.Structure):
                 ("candidates", ctypes.c_uint32)]
 
 
+class fz_server_cfg(ctypes.Structure):
+    _fields_ = [("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("mem_budget", ctypes.c_uint64), ("max_store_tuples", ctypes.c_uint64)]
+
+
+class fz_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
+                ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
+                ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double)]
+
+
 MODES = {"count": 0, "hist": 1, "exists": 2, "store": 3}
 
 _u64, _u32, _i64 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64
@@ -103,6 +115,12 @@ _SIGS = {
     "fz_last_error": (ctypes.c_char_p, []),
     "fz_autotune": (ctypes.c_int, [ctypes.POINTER(fz_query), _u32, _u32,
                                    ctypes.POINTER(fz_tune_result)]),
+    "fz_server_create": (ctypes.c_int, [ctypes.POINTER(fz_server_cfg),
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "fz_submit": (ctypes.c_int, [_vp, ctypes.POINTER(fz_query), _u64p]),
+    "fz_wait": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(fz_result)]),
+    "fz_server_stats_read": (ctypes.c_int, [_vp, ctypes.POINTER(fz_server_stats), ctypes.c_int]),
+    "fz_server_destroy": (ctypes.c_int, [_vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -247,18 +265,7 @@ def batch(queries, stream=None):
     qarr, keep = _marshal(queries)
     rarr = (fz_result * max(nq, 1))()
     _check(_lib.fz_batch(qarr, rarr, nq, _vp(stream) if stream else None), "fz_batch")
-    res = []
-    for i, q in enumerate(queries):
-        r = rarr[i]
-        d = dict(status=r.status, count=r.count, total=r.total, found=bool(r.found))
-        if q["mode"] == "hist":
-            d["bins"] = q.pop("_bins")
-            d["min_len"] = None if r.min_len == 2**64 - 1 else r.min_len
-            d["max_len"] = None if r.min_len == 2**64 - 1 else r.max_len
-        if q["mode"] == "store":
-            d["written"] = r.written
-        res.append(d)
-    return res
+    return [_result_dict(q, rarr[i]) for i, q in enumerate(queries)]
 
 
 def autotune(queries, reps: int = 3) -> dict:
@@ -271,6 +278,67 @@ def autotune(queries, reps: int = 3) -> dict:
     for q in queries:
         q.pop("_bins", None)
     return {k: getattr(out, k) for k, _ in fz_tune_result._fields_}
+
+
+def _result_dict(q, r):
+    d = dict(status=r.status, count=r.count, total=r.total, found=bool(r.found))
+    if q["mode"] == "hist":
+        d["bins"] = q.pop("_bins", None)
+        d["min_len"] = None if r.min_len == 2**64 - 1 else r.min_len
+        d["max_len"] = None if r.min_len == 2**64 - 1 else r.max_len
+    if q["mode"] == "store":
+        d["written"] = r.written
+    return d
+
+
+class Server:
+    """fz_server: submit queries (dicts as for batch) one at a time, collect
+    each result with wait(ticket).  The library's own thread batches what has
+    arrived onto up to max_inflight streams."""
+
+    def __init__(self, max_inflight=0, max_batch=0, mem_budget=0, max_store_tuples=0):
+        cfg = fz_server_cfg(max_inflight, max_batch, mem_budget, max_store_tuples)
+        h = ctypes.c_void_p()
+        _check(_lib.fz_server_create(ctypes.byref(cfg), ctypes.byref(h)), "fz_server_create")
+        self._h = h
+        self._live = {}  # ticket -> (query, host buffers it points to)
+
+    def submit(self, q) -> int:
+        qarr, keep = _marshal([q])
+        t = ctypes.c_uint64(0)
+        _check(_lib.fz_submit(self._h, qarr, ctypes.byref(t)), "fz_submit")
+        self._live[t.value] = (q, keep)
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        r = fz_result()
+        _check(_lib.fz_wait(self._h, ticket, ctypes.byref(r)), "fz_wait")
+        q, _ = self._live.pop(ticket)
+        return _result_dict(q, r)
+
+    def stats(self, reset=False) -> dict:
+        st = fz_server_stats()
+        _check(_lib.fz_server_stats_read(self._h, ctypes.byref(st), 1 if reset else 0),
+               "fz_server_stats_read")
+        return {k: getattr(st, k) for k, _ in fz_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_lib.fz_server_destroy(self._h), "fz_server_destroy")
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def last_stats() -> dict:

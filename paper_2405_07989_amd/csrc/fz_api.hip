@@ -14,9 +14,10 @@
 #include <vector>
 
 #include "fz.h"
+#include "fz_host.h"
 #include "fz_internal.h"
 
-namespace {
+namespace fzh {
 
 constexpr int kMaxDevices = 64;
 constexpr uint32_t kDefaultSlicesPerWave = 16;
@@ -36,11 +37,6 @@ constexpr double kWorkChunk = 23.0 * 64;
 constexpr double kWorkTrip = 7.0 * 64;
 constexpr double kWorkElem[4] = {4, 8, 5, 40}; // count, hist, exists, store
 
-struct DevBuf {
-    void *p = nullptr;
-    size_t cap = 0;
-};
-
 struct Ctx {
     bool ready = false;
     int device = -1;
@@ -48,11 +44,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     FzCtl *host_ctl = nullptr; // pinned
     DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out;
-    // batches
-    DevBuf b_meta, b_tables, b_restabs, b_bounds, b_base, b_recs, b_bins, b_res, b_cursor;
-    std::vector<uint8_t> b_host;
-    FzBatchResult *b_res_host = nullptr; // pinned
-    size_t b_res_cap = 0;
+    BatchSlot batch; // fz_batch
     fz_stats last{};
 };
 
@@ -431,26 +423,53 @@ double estimate_work(const FzPlan &P)
            P.w_el * el;
 }
 
-template <class T> T *stage(std::vector<uint8_t> &buf, size_t &off, size_t count)
+void current_knobs(uint32_t *spw, uint32_t *wgcu)
 {
-    off = (off + 63) & ~(size_t)63;
-    T *p = (T *)(buf.data() + off);
-    off += count * sizeof(T);
-    return p;
+    *spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
+    *wgcu = g_wg_per_cu ? g_wg_per_cu : kDefaultWgPerCu;
 }
 
-int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
+hipError_t ensure_pinned(void **p, size_t *cap, size_t bytes)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
-    Ctx *cp;
-    int rc = get_ctx(&cp);
-    if (rc) return rc;
-    Ctx &c = *cp;
-    hipStream_t st = stream ? (hipStream_t)stream : c.stream;
+    if (bytes <= *cap && *p) return hipSuccess;
+    if (*p) (void)hipHostFree(*p);
+    *p = nullptr;
+    *cap = 0;
+    const size_t want = std::max(bytes, (size_t)4096);
+    hipError_t e = hipHostMalloc(p, want, hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return e;
+    }
+    *cap = want;
+    return hipSuccess;
+}
 
+void BatchSlot::release()
+{
+    for (DevBuf *b : {&meta, &tables, &restabs, &bounds, &base, &recs, &bins, &res, &cursor}) {
+        if (b->p) (void)hipFree(b->p);
+        b->p = nullptr;
+        b->cap = 0;
+    }
+    for (void **h : {(void **)&h_meta, (void **)&h_res, (void **)&h_done, (void **)&h_bins}) {
+        if (*h) (void)hipHostFree(*h);
+        *h = nullptr;
+    }
+    h_meta_cap = 0;
+    h_cap = 0;
+    h_bins_cap = 0;
+}
+
+int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
+                 uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile)
+{
     // plans; a rejected query keeps d = 0 and takes no device work
-    std::vector<FzBatchQuery> Q(nq);
-    std::vector<int> qst(nq, FZ_OK);
+    std::vector<FzBatchQuery> &Q = S.Q;
+    Q.assign(nq, FzBatchQuery{});
+    S.qst.assign(nq, FZ_OK);
+    S.nq = nq;
     std::vector<double> work(nq, 0.0);
     double total_work = 0;
     uint32_t maxm = 0, max_du = 0, bstride = 1;
@@ -458,18 +477,19 @@ int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
     for (uint32_t i = 0; i < nq; ++i) {
         std::memset(&Q[i], 0, sizeof(FzBatchQuery));
         const fz_query &q = qs[i];
-        if (q.mode > FZ_MODE_STORE) { qst[i] = FZ_EINVAL; continue; }
+        if (q.mode > FZ_MODE_STORE) { S.qst[i] = FZ_EINVAL; continue; }
         FzPlan &P = Q[i].plan;
         int e = make_plan(q.n, q.g, q.d, q.mode, &P);
         if (!e && q.mode == FZ_MODE_HIST && (q.bins == nullptr || q.nbins < P.nbins)) e = FZ_EINVAL;
         if (!e && q.mode == FZ_MODE_STORE && q.d_out == nullptr && q.max_tuples > 0) e = FZ_EINVAL;
         if (e) {
-            qst[i] = e;
+            S.qst[i] = e;
             std::memset(&P, 0, sizeof P);
             continue;
         }
         P.target_len = q.target_len;
         if (q.mode == FZ_MODE_STORE) P.max_tuples = q.max_tuples;
+        Q[i].max_total = store_cap;
         work[i] = estimate_work(P);
         total_work += work[i];
         maxm = std::max(maxm, P.d - 3);
@@ -477,9 +497,7 @@ int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
         if (q.mode == FZ_MODE_STORE) max_du = std::max(max_du, P.d_user);
         if (q.mode == FZ_MODE_HIST) any_hist = true;
     }
-    const uint32_t wgcu = g_wg_per_cu ? g_wg_per_cu : kDefaultWgPerCu;
-    const uint32_t spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
-    const double waves = (double)c.cus * wgcu * (FZK_WG / FZK_WAVE);
+    const double waves = (double)cus * wgcu * (FZK_WG / FZK_WAVE);
     const double target = std::max(total_work / (waves * spw), 1.0);
     const uint32_t lds_bins = any_hist ? kBatchLdsBins : 0;
 
@@ -526,114 +544,161 @@ int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
         Q[i].item_off = n_items;
         n_items += Q[i].n_slices;
     }
+    S.n_items = n_items;
 
-    // host staging: queries, boundary jobs, items, ids of sliced queries
-    size_t off = 0;
-    c.b_host.resize(64 + nq * sizeof(FzBatchQuery) + (size_t)n_bounds * sizeof(FzBatchJob) +
-                    (size_t)n_items * sizeof(FzBatchJob) + sliced_ids.size() * 4 + 4 * 64);
-    FzBatchQuery *hq = stage<FzBatchQuery>(c.b_host, off, nq);
-    const size_t o_jobs = (off + 63) & ~(size_t)63;
-    FzBatchJob *hj = stage<FzBatchJob>(c.b_host, off, n_bounds);
-    const size_t o_items = (off + 63) & ~(size_t)63;
-    FzBatchJob *hi = stage<FzBatchJob>(c.b_host, off, n_items);
-    const size_t o_ids = (off + 63) & ~(size_t)63;
-    uint32_t *hids = stage<uint32_t>(c.b_host, off, sliced_ids.size());
-    std::memcpy(hq, Q.data(), nq * sizeof(FzBatchQuery));
+    // pinned staging: queries, boundary jobs, items, ids of sliced queries
+    auto up = [](size_t o) { return (o + 63) & ~(size_t)63; };
+    const size_t o_q = 0;
+    const size_t o_jobs = up(o_q + (size_t)nq * sizeof(FzBatchQuery));
+    const size_t o_items = up(o_jobs + (size_t)n_bounds * sizeof(FzBatchJob));
+    const size_t o_ids = up(o_items + (size_t)n_items * sizeof(FzBatchJob));
+    const size_t meta_bytes = up(o_ids + sliced_ids.size() * 4);
+    FZ_TRY(ensure_pinned((void **)&S.h_meta, &S.h_meta_cap, meta_bytes));
+    if (S.h_cap < nq) {
+        size_t c1 = 0, c2 = 0;
+        if (S.h_res) (void)hipHostFree(S.h_res);
+        if (S.h_done) (void)hipHostFree(S.h_done);
+        S.h_res = nullptr;
+        S.h_done = nullptr;
+        S.h_cap = 0;
+        FZ_TRY(ensure_pinned((void **)&S.h_res, &c1, (size_t)nq * sizeof(FzBatchResult)));
+        FZ_TRY(ensure_pinned((void **)&S.h_done, &c2, (size_t)nq * 4));
+        S.h_cap = nq;
+    }
+    {
+        size_t cap = S.h_bins_cap * 8;
+        FZ_TRY(ensure_pinned((void **)&S.h_bins, &cap, std::max<size_t>(bin_words, 1) * 8));
+        S.h_bins_cap = cap / 8;
+    }
+    uint8_t *hm = S.h_meta;
+    std::memcpy(hm + o_q, Q.data(), (size_t)nq * sizeof(FzBatchQuery));
+    FzBatchJob *hj = (FzBatchJob *)(hm + o_jobs);
+    FzBatchJob *hi = (FzBatchJob *)(hm + o_items);
     for (uint32_t i : order) {
         for (uint32_t j = 0; j <= Q[i].n_slices; ++j) hj[Q[i].bound_off + j] = {i, j};
         for (uint32_t j = 0; j < Q[i].n_slices; ++j) hi[Q[i].item_off + j] = {i, j};
     }
-    std::memcpy(hids, sliced_ids.data(), sliced_ids.size() * 4);
+    if (!sliced_ids.empty())
+        std::memcpy(hm + o_ids, sliced_ids.data(), sliced_ids.size() * 4);
+    std::memset(S.h_done, 0, (size_t)nq * 4);
+    std::memset(S.h_res, 0, (size_t)nq * sizeof(FzBatchResult));
 
-    FZ_TRY(ensure(c.b_meta, off));
-    FZ_TRY(ensure(c.b_tables, tab_words * 8));
-    FZ_TRY(ensure(c.b_restabs, res_words * sizeof(int2)));
-    FZ_TRY(ensure(c.b_bounds, (size_t)n_bounds * bstride * 4));
-    FZ_TRY(ensure(c.b_base, (size_t)n_bounds * 8));
-    FZ_TRY(ensure(c.b_recs, (size_t)std::max(n_items, 1u) * sizeof(FzSliceRec)));
-    FZ_TRY(ensure(c.b_bins, bin_words * 8));
-    FZ_TRY(ensure(c.b_res, (size_t)nq * sizeof(FzBatchResult)));
-    FZ_TRY(ensure(c.b_cursor, 256));
-    if (c.b_res_cap < nq) {
-        if (c.b_res_host) (void)hipHostFree(c.b_res_host);
-        c.b_res_host = nullptr;
-        c.b_res_cap = 0;
-        FZ_TRY(hipHostMalloc((void **)&c.b_res_host, (size_t)nq * sizeof(FzBatchResult),
-                             hipHostMallocDefault));
-        c.b_res_cap = nq;
-    }
-    uint8_t *meta = (uint8_t *)c.b_meta.p;
-    FZ_TRY(hipMemcpyAsync(meta, c.b_host.data(), off, hipMemcpyHostToDevice, st));
+    FZ_TRY(ensure(S.meta, meta_bytes));
+    FZ_TRY(ensure(S.tables, tab_words * 8));
+    FZ_TRY(ensure(S.restabs, res_words * sizeof(int2)));
+    FZ_TRY(ensure(S.bounds, (size_t)n_bounds * bstride * 4));
+    FZ_TRY(ensure(S.base, (size_t)n_bounds * 8));
+    FZ_TRY(ensure(S.recs, (size_t)std::max(n_items, 1u) * sizeof(FzSliceRec)));
+    FZ_TRY(ensure(S.bins, bin_words * 8));
+    FZ_TRY(ensure(S.res, (size_t)nq * sizeof(FzBatchResult)));
+    FZ_TRY(ensure(S.cursor, 256));
+    uint8_t *meta = (uint8_t *)S.meta.p;
+    FZ_TRY(hipMemcpyAsync(meta, hm, meta_bytes, hipMemcpyHostToDevice, st));
 
     FzBatchBufs B;
-    B.queries = (const FzBatchQuery *)meta;
+    B.queries = (const FzBatchQuery *)(meta + o_q);
     B.bjobs = (const FzBatchJob *)(meta + o_jobs);
     B.items = (const FzBatchJob *)(meta + o_items);
-    B.tables = (uint64_t *)c.b_tables.p;
-    B.restabs = (int2 *)c.b_restabs.p;
-    B.bounds = (uint32_t *)c.b_bounds.p;
-    B.base = (uint64_t *)c.b_base.p;
-    B.recs = (FzSliceRec *)c.b_recs.p;
-    B.bins = (uint64_t *)c.b_bins.p;
-    B.res = (FzBatchResult *)c.b_res.p;
-    B.cursor = (uint32_t *)c.b_cursor.p;
+    B.tables = (uint64_t *)S.tables.p;
+    B.restabs = (int2 *)S.restabs.p;
+    B.bounds = (uint32_t *)S.bounds.p;
+    B.base = (uint64_t *)S.base.p;
+    B.recs = (FzSliceRec *)S.recs.p;
+    B.bins = (uint64_t *)S.bins.p;
+    B.res = (FzBatchResult *)S.res.p;
+    B.cursor = (uint32_t *)S.cursor.p;
+    B.host_res = S.h_res;
+    B.host_bins = S.h_bins;
+    B.host_done = S.h_done;
     B.nq = nq;
     B.n_bjobs = n_bounds;
     B.n_items = n_items;
     B.bstride = bstride;
     B.n_bins = bin_words;
-    const uint32_t nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
+    if (n_items == 0) return FZ_OK; // every query was rejected on the host
+    const uint32_t nwg = (uint32_t)std::min<uint64_t>((uint64_t)cus * wgcu,
                                                       std::max<uint32_t>(1, (n_items + 3) / 4));
-    FZ_LAUNCH("batch.prep", st,
-              fzk_launch_batch_prep(B, (uint32_t)sliced_ids.size(),
-                                    (const uint32_t *)(meta + o_ids), st));
-    FZ_LAUNCH("batch.walk", st, fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
-    FZ_LAUNCH("batch.finalize", st, fzk_launch_batch_finalize(B, st));
-    FZ_TRY(hipMemcpyAsync(c.b_res_host, B.res, (size_t)nq * sizeof(FzBatchResult),
-                          hipMemcpyDeviceToHost, st));
-    std::vector<uint64_t> bins(bin_words);
-    if (bin_words)
-        FZ_TRY(hipMemcpyAsync(bins.data(), B.bins, bin_words * 8, hipMemcpyDeviceToHost, st));
-    FZ_TRY(hipStreamSynchronize(st));
-    prof_collect();
-
-    for (uint32_t i = 0; i < nq; ++i) {
-        fz_result &r = rs[i];
-        std::memset(&r, 0, sizeof r);
-        r.min_len = UINT64_MAX;
-        if (qst[i]) {
-            r.status = qst[i];
-            continue;
-        }
-        const FzBatchResult &h = c.b_res_host[i];
-        const FzPlan &P = Q[i].plan;
-        if (h.status & FZS_OVERFLOW) { r.status = FZ_EOVERFLOW; continue; }
-        if (h.status & FZS_MISMATCH) { r.status = FZ_EINTERNAL; continue; }
-        r.count = h.count;
-        r.total = Q[i].sliced ? h.total : h.count;
-        r.found = h.found ? 1 : 0;
-        r.status = FZ_OK;
-        if (P.mode == FZM_HIST) {
-            uint64_t sum = 0;
-            for (uint32_t l = 0; l < P.nbins; ++l) sum += bins[Q[i].bins_off + l];
-            if (sum != h.count) { r.status = FZ_EINTERNAL; continue; }
-            std::memcpy(qs[i].bins, bins.data() + Q[i].bins_off, (size_t)P.nbins * 8);
-            for (uint64_t l = P.nbins; l < qs[i].nbins; ++l) qs[i].bins[l] = 0;
-            r.min_len = h.count ? h.min_len : UINT64_MAX;
-            r.max_len = h.count ? h.max_len : 0;
-        }
-        if (P.mode == FZM_STORE) {
-            r.written = h.count;
-            if (h.count != std::min(h.total, P.max_tuples)) { r.status = FZ_EINTERNAL; continue; }
-            if (h.total > P.max_tuples) r.status = FZ_TRUNCATED;
-        }
-        if (P.mode == FZM_COUNT && Q[i].sliced && h.count != h.total) r.status = FZ_EINTERNAL;
+    const uint32_t *ids = (const uint32_t *)(meta + o_ids);
+    const uint32_t n_sliced = (uint32_t)sliced_ids.size();
+    if (profile) {
+        FZ_LAUNCH("batch.prep", st, fzk_launch_batch_prep(B, n_sliced, ids, st));
+        FZ_LAUNCH("batch.walk", st, fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
+    } else {
+        FZ_TRY(fzk_launch_batch_prep(B, n_sliced, ids, st));
+        FZ_TRY(fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
     }
-    c.last.slices = n_items;
     return FZ_OK;
 }
 
-} // namespace
+void batch_result(const BatchSlot &S, const fz_query &q, uint32_t i, fz_result *out)
+{
+    fz_result r;
+    std::memset(&r, 0, sizeof r);
+    r.min_len = UINT64_MAX;
+    if (S.qst[i]) {
+        r.status = S.qst[i];
+        *out = r;
+        return;
+    }
+    const FzBatchResult h = S.h_res[i];
+    const FzBatchQuery &B = S.Q[i];
+    const FzPlan &P = B.plan;
+    r.total = B.sliced ? h.total : h.count;
+    if (h.status & FZS_OVERFLOW) r.status = FZ_EOVERFLOW;
+    else if (h.status & FZS_TOOBIG) r.status = FZ_E2BIG;
+    else if (h.status & FZS_MISMATCH) r.status = FZ_EINTERNAL;
+    if (r.status) {
+        *out = r;
+        return;
+    }
+    r.count = h.count;
+    r.found = h.found ? 1 : 0;
+    r.status = FZ_OK;
+    if (P.mode == FZM_HIST) {
+        const uint64_t *bins = S.h_bins + B.bins_off;
+        uint64_t sum = 0;
+        for (uint32_t l = 0; l < P.nbins; ++l) sum += bins[l];
+        if (sum != h.count) {
+            r.status = FZ_EINTERNAL;
+        } else {
+            std::memcpy(q.bins, bins, (size_t)P.nbins * 8);
+            for (uint64_t l = P.nbins; l < q.nbins; ++l) q.bins[l] = 0;
+            r.min_len = h.count ? h.min_len : UINT64_MAX;
+            r.max_len = h.count ? h.max_len : 0;
+        }
+    } else if (P.mode == FZM_STORE) {
+        r.written = h.count;
+        if (h.count != std::min(h.total, P.max_tuples)) r.status = FZ_EINTERNAL;
+        else if (h.total > P.max_tuples) r.status = FZ_TRUNCATED;
+    } else if (B.sliced && h.count != h.total && !(P.mode == FZM_EXISTS && h.found)) {
+        // without an early exit every slice ran to its end: all of Z
+        r.status = FZ_EINTERNAL;
+    }
+    *out = r;
+}
+
+int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    Ctx *cp;
+    int rc = get_ctx(&cp);
+    if (rc) return rc;
+    Ctx &c = *cp;
+    hipStream_t st = stream ? (hipStream_t)stream : c.stream;
+    uint32_t spw, wgcu;
+    current_knobs(&spw, &wgcu);
+    rc = batch_launch(c.batch, c.cus, spw, wgcu, qs, nq, st, UINT64_MAX, true);
+    if (rc) return rc;
+    FZ_TRY(hipStreamSynchronize(st));
+    prof_collect();
+    for (uint32_t i = 0; i < nq; ++i) batch_result(c.batch, qs[i], i, &rs[i]);
+    c.last.slices = c.batch.n_items;
+    return FZ_OK;
+}
+
+} // namespace fzh
+
+using namespace fzh;
 
 extern "C" {
 

@@ -1,0 +1,66 @@
+// fz_host.h -- host-side pieces shared by the libfz entry points (fz_api.hip)
+// and the request server (fz_server.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <vector>
+
+#include "fz.h"
+#include "fz_internal.h"
+
+namespace fzh {
+
+// Grow-only device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+hipError_t ensure(DevBuf &b, size_t bytes);
+
+// Records a failed HIP call for fz_last_error; FZ_ENOMEM or FZ_EDEVICE.
+int dev_err_at(hipError_t e, const char *what, int line);
+
+// Validation and normalization of one query (every limit of include/fz.h).
+int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *P);
+
+// Serializes the library's entry points and guards the tuning knobs.
+extern std::mutex g_mu;
+
+// One batch: device buffers, pinned host arrays the walker writes finished
+// queries into (coherent, so the host may read them while the launch runs),
+// and the plan of the batch last launched from it.  fz_batch uses one per
+// device; a server owns one per launch slot.
+struct BatchSlot {
+    DevBuf meta, tables, restabs, bounds, base, recs, bins, res, cursor;
+    uint8_t *h_meta = nullptr;   // pinned staging of queries, jobs and items
+    size_t h_meta_cap = 0;
+    FzBatchResult *h_res = nullptr;
+    uint32_t *h_done = nullptr;
+    uint32_t h_cap = 0;          // queries h_res / h_done hold
+    uint64_t *h_bins = nullptr;
+    uint64_t h_bins_cap = 0;     // words
+    std::vector<FzBatchQuery> Q;
+    std::vector<int> qst;        // host validation status of each query
+    uint32_t nq = 0, n_items = 0;
+    void release();
+};
+
+// Plans qs[0..nq) and queues the whole batch on stream st (count and work
+// tables, residue tables, slice bounds, the persistent walker); returns
+// without waiting.  Store queries with |Z| > store_cap are refused on the
+// device (FZ_E2BIG).  Requires g_mu held when profile is true.  The slot's
+// previous launch must have completed.
+int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
+                 uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile);
+
+// Result of query i of the slot's batch, once h_done[i] is set or the stream
+// has completed (host-rejected queries have their status at once).  Copies
+// histogram bins to q.bins.
+void batch_result(const BatchSlot &S, const fz_query &q, uint32_t i, fz_result *r);
+
+// Effective slices-per-wave and workgroups-per-CU knobs (g_mu held).
+void current_knobs(uint32_t *spw, uint32_t *wgcu);
+
+} // namespace fzh

@@ -73,7 +73,7 @@ struct FzCtl {
     uint64_t written;
 };
 
-enum { FZS_OVERFLOW = 1u, FZS_MISMATCH = 2u };
+enum { FZS_OVERFLOW = 1u, FZS_MISMATCH = 2u, FZS_TOOBIG = 4u };
 
 // Per-slice record written by the walker (one wave per slice).
 struct FzSliceRec {
@@ -110,13 +110,15 @@ struct FzBatchQuery {
     uint64_t tab_off;     // residue table (2B int2)
     uint64_t bins_off;    // histogram bins (nbins u64), hist queries
     uint32_t *out;        // store destination (device), store queries
+    uint64_t max_total;   // a store query with |Z| above this is refused (FZS_TOOBIG)
     uint32_t sliced;      // 1: count/work tables and W_q rank-cut slices
     uint32_t n_slices;    // W_q
     uint32_t bound_off;   // first boundary of this query in the bounds array
     uint32_t item_off;    // first walker item of this query
 };
 
-// Per-query result in device memory.
+// Per-query result in device memory.  The walkers add their items' counts;
+// the wave that completes a query's last item (items_done) finishes it.
 struct FzBatchResult {
     uint64_t count;       // elements the walkers visited
     uint64_t total;       // |Z| from the count table (sliced queries)
@@ -124,6 +126,8 @@ struct FzBatchResult {
     uint64_t written;
     uint32_t found;
     uint32_t status;      // FZS_* bits
+    uint32_t items_done;
+    uint32_t pad;
 };
 
 // A boundary job of the batch slice kernel / a walker work item.
@@ -144,6 +148,12 @@ struct FzBatchBufs {
     uint64_t *bins;            // histogram bins of hist queries
     FzBatchResult *res;        // per query
     uint32_t *cursor;          // walker item cursor (own 128-byte line)
+    // optional host-visible copies (pinned, coherent): a finished query's
+    // result and bins are written there and host_done[q] is set to 1 with a
+    // system-scope release, so the host can collect it while the launch runs
+    FzBatchResult *host_res;
+    uint64_t *host_bins;
+    uint32_t *host_done;
     uint32_t nq, n_bjobs, n_items, bstride;
     uint64_t n_bins;           // words of the histogram buffer
 };
@@ -159,9 +169,8 @@ hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *r
                              uint64_t nranks, uint32_t *out, hipStream_t s);
 size_t fzk_enum_lds_bytes(const FzPlan &p);
 // batch: zeroing, count / work tables, residue tables and slice bounds; then
-// the persistent walker; then the per-query finalize
+// the persistent walker, which also finishes each query
 hipError_t fzk_launch_batch_prep(const FzBatchBufs &b, uint32_t n_sliced,
                                  const uint32_t *sliced_ids, hipStream_t s);
 hipError_t fzk_launch_batch_walk(const FzBatchBufs &b, uint32_t maxm, uint32_t nwg,
                                  uint32_t lds_bins, uint32_t max_du, hipStream_t s);
-hipError_t fzk_launch_batch_finalize(const FzBatchBufs &b, hipStream_t s);

@@ -861,8 +861,113 @@ __global__ void fz_batch_slices_kernel(FzBatchBufs B)
         const uint64_t N = S[P.n];
         B.res[job.q].total = N;
         if (N == ~0ull || C[P.n] == ~0ull) B.res[job.q].status = FZS_OVERFLOW;
+        else if (P.mode == FZM_STORE && N > Q.max_total) B.res[job.q].status = FZS_TOOBIG;
     }
     B.base[bi] = slice_bound(P, S, C, Q.n_slices, job.j, out);
+}
+
+// integrate_hist for one wavefront (no workgroup barrier): lane l takes
+// chain l % s and band l / s of it when s < 64, else whole chains.
+__device__ void wave_integrate(uint64_t *h, uint32_t nb, uint32_t s, uint32_t lane)
+{
+    if (s == 0 || s >= nb) return;
+    if (s >= FZK_WAVE) {
+        for (uint32_t c = lane; c < s; c += FZK_WAVE) {
+            uint64_t acc = 0;
+            for (uint32_t v = c; v < nb; v += s) {
+                acc += h[v];
+                h[v] = acc;
+            }
+        }
+        return;
+    }
+    const uint32_t bands = FZK_WAVE / s;
+    const uint32_t rows = (nb + s - 1) / s;
+    const uint32_t per = (rows + bands - 1) / bands;
+    const uint32_t c = lane % s, b = lane / s;
+    const uint32_t k0 = b < bands ? b * per : rows;
+    const uint32_t k1 = b < bands ? min(rows, k0 + per) : rows;
+    uint64_t sum = 0;
+    for (uint32_t k = k0; k < k1; k += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t v = (uint64_t)(k + j) * s + c;
+            x[j] = (k + j < k1 && v < nb) ? h[v] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) sum += x[j];
+    }
+    uint64_t carry = 0;
+    for (uint32_t bb = 0; bb < bands; ++bb) {
+        const uint64_t x = __shfl(sum, (int)(bb * s + c));
+        if (bb < b) carry += x;
+    }
+    for (uint32_t k = k0; k < k1; k += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t v = (uint64_t)(k + j) * s + c;
+            x[j] = (k + j < k1 && v < nb) ? h[v] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint64_t v = (uint64_t)(k + j) * s + c;
+            carry += x[j];
+            if (k + j < k1 && v < nb) h[v] = carry;
+        }
+    }
+}
+
+// The last step of a batch query, by the wave that completed its last item:
+// the histogram's integration and min / max length, rows written, and the
+// host-visible copy with its flag.
+__device__ void finish_query(const FzBatchBufs &B, uint32_t q, const FzBatchQuery &Q,
+                             const FzPlan &P, uint32_t lane)
+{
+    FzBatchResult &R = B.res[q];
+    const uint32_t status = uni(R.status);
+    uint64_t lo = ~0ull, hi = 0;
+    if (P.mode == FZM_HIST && !(status & (FZS_OVERFLOW | FZS_TOOBIG))) {
+        uint64_t *bins = B.bins + Q.bins_off;
+        const int32_t step = (int32_t)(P.ord - P.delta);
+        wave_integrate(bins, P.nbins, step < 0 ? (uint32_t)-step : (uint32_t)step, lane);
+        for (uint32_t l = lane; l < P.nbins; l += FZK_WAVE) {
+            const uint64_t h = bins[l];
+            if (h) {
+                lo = l < lo ? l : lo;
+                hi = l > hi ? l : hi;
+            }
+            if (B.host_bins) B.host_bins[Q.bins_off + l] = h;
+        }
+        for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
+            const uint64_t lo2 = __shfl_xor(lo, o), hi2 = __shfl_xor(hi, o);
+            lo = lo2 < lo ? lo2 : lo;
+            hi = hi2 > hi ? hi2 : hi;
+        }
+    }
+    if (lane == 0) {
+        const uint64_t count = R.count;
+        R.min_len = lo;
+        R.max_len = hi;
+        R.written = P.mode == FZM_STORE ? count : 0;
+        if (B.host_res) {
+            FzBatchResult *H = B.host_res + q;
+            H->count = count;
+            H->total = R.total;
+            H->min_len = lo;
+            H->max_len = hi;
+            H->written = P.mode == FZM_STORE ? count : 0;
+            H->found = R.found;
+            H->status = R.status;
+            H->items_done = R.items_done;
+        }
+    }
+    if (B.host_done) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        if (lane == 0)
+            __hip_atomic_store(&B.host_done[q], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 template <int MAXM>
@@ -899,14 +1004,18 @@ __global__ void __launch_bounds__(FZK_WG)
         const uint32_t mode = uni(P.mode);
         WalkOut o;
         o.elements = o.rows = o.prefixes = 0;
-        bool skip = false;
+        // nothing to walk for a refused query, nor for a predicate already
+        // satisfied (status and found were set by earlier kernels or waves)
+        const uint32_t st0 = uni(__hip_atomic_load(&B.res[q].status, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT));
+        bool skip = (st0 & (FZS_OVERFLOW | FZS_TOOBIG)) != 0;
         if (mode == FZM_EXISTS) {
             const uint32_t f =
                 __hip_atomic_load(&B.res[q].found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            skip = uni(f) != 0;
+            skip = skip || uni(f) != 0;
         }
+        const uint32_t bi = Q.bound_off + s;
         if (!skip) {
-            const uint32_t bi = Q.bound_off + s;
             const uint32_t *b0 = B.bounds + (uint64_t)bi * B.bstride;
             const uint32_t *b1 = b0 + B.bstride;
             const uint64_t base = B.base[bi];
@@ -942,67 +1051,24 @@ __global__ void __launch_bounds__(FZK_WG)
         rec.t_begin = t_begin;
         rec.t_end = wall_clock64();
         B.recs[it] = rec; // the same value from every lane
-    }
-}
 
-// One workgroup per query: element total and the slice self-check (sliced
-// queries), the histogram's integration and min / max length, rows written
-// (stores).
-__global__ void __launch_bounds__(FZK_WG) fz_batch_finalize_kernel(FzBatchBufs B)
-{
-    __shared__ uint64_t part[FZK_WG];
-    __shared__ uint64_t red[4][FZK_WG / FZK_WAVE];
-    const uint32_t tid = threadIdx.x, lane = tid % FZK_WAVE, w = tid / FZK_WAVE;
-    const uint32_t q = blockIdx.x;
-    const FzBatchQuery &Q = B.queries[q];
-    const FzPlan P = Q.plan;
-    FzBatchResult &R = B.res[q];
-    if (P.d == 0) return; // rejected query: the whole workgroup leaves
-    uint64_t el = 0, bad = 0;
-    for (uint32_t s = tid; s < Q.n_slices; s += FZK_WG) {
-        const uint64_t e = B.recs[Q.item_off + s].elements;
-        el += e;
-        if (Q.sliced && P.mode != FZM_EXISTS) {
-            const uint64_t want = B.base[Q.bound_off + s + 1] - B.base[Q.bound_off + s];
-            if (e != want) bad = 1;
+        // The item's share of its query, then the item count: the wave that
+        // completes the query's last item finishes the query.  Each slice of
+        // a cut query must have produced exactly its rank range.
+        FzBatchResult &R = B.res[q];
+        const bool bad = !skip && Q.sliced && mode != FZM_EXISTS &&
+                         o.elements != B.base[bi + 1] - B.base[bi];
+        if (lane == 0) {
+            if (o.elements) atomicAdd((unsigned long long *)&R.count, o.elements);
+            if (bad) atomicOr(&R.status, FZS_MISMATCH);
         }
-    }
-    uint64_t lo = ~0ull, hi = 0;
-    if (P.mode == FZM_HIST) {
-        uint64_t *bins = B.bins + Q.bins_off;
-        integrate_hist(P, bins, part);
-        for (uint32_t l = tid; l < P.nbins; l += FZK_WG)
-            if (bins[l]) {
-                lo = l < lo ? l : lo;
-                hi = l > hi ? l : hi;
-            }
-    }
-    for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
-        el += __shfl_xor(el, o);
-        bad |= __shfl_xor(bad, o);
-        const uint64_t lo2 = __shfl_xor(lo, o), hi2 = __shfl_xor(hi, o);
-        lo = lo2 < lo ? lo2 : lo;
-        hi = hi2 > hi ? hi2 : hi;
-    }
-    if (lane == 0) {
-        red[0][w] = el;
-        red[1][w] = bad;
-        red[2][w] = lo;
-        red[3][w] = hi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        for (uint32_t i = 1; i < FZK_WG / FZK_WAVE; ++i) {
-            el += red[0][i];
-            bad |= red[1][i];
-            lo = red[2][i] < lo ? red[2][i] : lo;
-            hi = red[3][i] > hi ? red[3][i] : hi;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const uint32_t old_done = atomicAdd(&R.items_done, lane == 0 ? 1u : 0u);
+        const uint32_t done = __builtin_amdgcn_readlane(old_done, 0) + 1;
+        if (done == uni(Q.n_slices)) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            finish_query(B, q, Q, P, lane);
         }
-        R.count = el;
-        if (bad) R.status |= FZS_MISMATCH;
-        R.min_len = lo;
-        R.max_len = hi;
-        R.written = P.mode == FZM_STORE ? el : 0;
     }
 }
 
@@ -1148,11 +1214,5 @@ hipError_t fzk_launch_batch_walk(const FzBatchBufs &b, uint32_t maxm, uint32_t n
 {
     if (maxm <= 5) launch_batch_enum<5>(b, nwg, lds_bins, max_du, s);
     else launch_batch_enum<13>(b, nwg, lds_bins, max_du, s);
-    return hipGetLastError();
-}
-
-hipError_t fzk_launch_batch_finalize(const FzBatchBufs &b, hipStream_t s)
-{
-    hipLaunchKernelGGL(fz_batch_finalize_kernel, dim3(b.nq), dim3(FZK_WG), 0, s, b);
     return hipGetLastError();
 }

@@ -14,6 +14,10 @@ Choices (the readings of the workload descriptions):
                  with |Z(n)| >= 1e11.
   batch          4096 queries; query i draws from SplitMix64(i-th output of
                  SplitMix64(master)) and draws again while |Z| > 1e8.
+  served         20000 queries drawn like the batch, 20% of them store
+                 queries; a draw is redrawn while |Z| > 1e8, or > 1e7 for a
+                 store query.  Kept: each query's seed-derived redraw count
+                 (fzinputs.served_query regenerates it) and |Z|.
 """
 import json
 import os
@@ -33,6 +37,9 @@ OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "workloads.json")
 BATCH_MASTER_SEED = 20240513
 BATCH_QUERIES = 4096
 BATCH_CAP = 10**8
+SERVED_MASTER_SEED = 20240514
+SERVED_QUERIES = 20000
+STORE_CAP = 10**7
 
 
 def single_small():
@@ -86,6 +93,30 @@ def batch():
     return dict(master_seed=BATCH_MASTER_SEED, cap=BATCH_CAP, redraws=redraws, queries=queries)
 
 
+def served():
+    seeds = fzinputs.query_seeds(SERVED_MASTER_SEED, SERVED_QUERIES)
+    redraws, counts, modes = [], [], []
+    for s in seeds:
+        rng = fzinputs.SplitMix64(s)
+        k = 0
+        while True:
+            q = fzinputs.draw_served(rng)
+            cap = STORE_CAP if q["mode"] == "store" else BATCH_CAP
+            try:
+                c = oracle.dp_count(q["n"], q["g"])
+            except OverflowError:
+                c = None
+            if c is not None and c <= cap:
+                break
+            k += 1
+        redraws.append(k)
+        counts.append(c)
+        modes.append(q["mode"])
+    return dict(master_seed=SERVED_MASTER_SEED, cap=BATCH_CAP, store_cap=STORE_CAP,
+                store_share=fzinputs.STORE_SHARE, redraws=redraws, counts=counts,
+                n_store=modes.count("store"))
+
+
 def main():
     t0 = time.time()
     out = dict(
@@ -94,6 +125,7 @@ def main():
         single_large=single_large(),
         length_set=length_set(),
         batch=batch(),
+        served=served(),
     )
     with open(OUT, "w") as f:
         json.dump(out, f, separators=(",", ":"))

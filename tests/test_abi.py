@@ -89,3 +89,19 @@ def test_batch_validation_without_a_device():
         with pytest.raises(fz.FzError) as e:
             fz.batch([dict(n=10, g=[3, 5], mode="count")])
         assert e.value.status == fz.FZ_EDEVICE
+
+
+def test_server_validation_without_a_device():
+    L = fz._lib
+    assert L.fz_server_create(None, None) == fz.FZ_EINVAL
+    cfg = fz.fz_server_cfg(9, 0, 0, 0)  # more than 8 launch slots
+    h = ctypes.c_void_p()
+    assert L.fz_server_create(ctypes.byref(cfg), ctypes.byref(h)) == fz.FZ_EINVAL
+    assert L.fz_submit(None, None, None) == fz.FZ_EINVAL
+    assert L.fz_wait(None, 1, None) == fz.FZ_EINVAL
+    assert L.fz_server_destroy(None) == fz.FZ_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(fz.FzError) as e:
+            fz.Server()
+        assert e.value.status == fz.FZ_EDEVICE
