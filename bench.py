@@ -8,11 +8,19 @@ store-mode enumeration of its 5e8 lex-smallest elements into a device buffer
 finalize kernels.  value = (|Z| + 5e8) / step time.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-batch] [--no-served]
+
+Beside the step, the same run measures (timed on their own, not part of the
+step): the 4096-query mixed batch in one launch ("batch"), and the served
+stream of 20000 queries through the request server against one launch per
+query ("served": closed-loop queries/s, p50/p99 latency at open-loop Poisson
+arrivals of half and nine tenths of that rate).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -91,12 +99,166 @@ def cpu_baseline(n, g, seconds_target=15.0):
                         f"of the same d=6 query, single-threaded C oracle"))
 
 
+def percentile(v, p):
+    v = sorted(v)
+    if not v:
+        return None
+    k = max(0, min(len(v) - 1, int(math.ceil(p * len(v))) - 1))
+    return v[k]
+
+
+def measure_batch(fz, reps=3):
+    """The 4096-query mixed batch (count / histogram / predicate) as one
+    fz_batch call; median of reps, every result checked against the stored
+    counts."""
+    import fzinputs
+    w = fzinputs.load_golden()["batch"]["queries"]
+    qs = [dict(n=q["n"], g=q["g"], mode=q["mode"], target_len=q["target_len"]) for q in w]
+    fz.batch(qs[:64])
+    times, walk, prep = [], [], []
+    for r in range(reps):
+        fz.profile_reset()
+        fz.profile_enable(True)
+        t0 = time.perf_counter()
+        res = fz.batch(qs)
+        times.append(time.perf_counter() - t0)
+        fz.profile_enable(False)
+        prep.append(fz.profile_read("batch.prep")[0])
+        walk.append(fz.profile_read("batch.walk")[0])
+        for q, x, ww in zip(qs, res, w):
+            ok = x["status"] == 0 and (x["count"] == ww["count"] or
+                                       (q["mode"] == "exists" and x["found"]))
+            if not ok:
+                raise RuntimeError(f"batch: wrong result for {q}: {x}")
+        log(f"batch rep {r + 1}/{reps}: {times[-1] * 1e3:.1f} ms")
+    t = sorted(times)[len(times) // 2]
+    elements = sum(x["count"] for x in w)
+    return {"queries": len(qs), "ms": t * 1e3, "queries_per_s": len(qs) / t,
+            "factorizations_per_s": elements / t,
+            "prep_ms": sorted(prep)[len(prep) // 2], "walk_ms": sorted(walk)[len(walk) // 2],
+            "workload": "4096 queries: d in 3..8, generators in [5,1000], n log-uniform in "
+                        "[1e3,1e6], |Z| <= 1e8, consumer count/hist/exists"}
+
+
+def _serve(fz, qs, gaps=None, inflight=4):
+    """Submits qs through one server (at the arrival gaps, or all at once),
+    collects every result on a second thread, and returns (elapsed s, server
+    stats, results)."""
+    import threading
+    import queue as qmod
+    srv = fz.Server(max_inflight=inflight)
+    pending = qmod.Queue()
+    results = [None] * len(qs)
+
+    def collector():
+        while True:
+            item = pending.get()
+            if item is None:
+                return
+            i, t = item
+            results[i] = srv.wait(t)
+
+    th = threading.Thread(target=collector)
+    th.start()
+    t0 = time.perf_counter()
+    next_t = t0
+    for i, q in enumerate(qs):
+        if gaps is not None:
+            next_t += gaps[i]
+            dt = next_t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+        pending.put((i, srv.submit(q)))
+    pending.put(None)
+    th.join()
+    elapsed = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return elapsed, st, results
+
+
+def measure_served(fz, torch, n_single=1000):
+    """The served stream: saturation (all 20000 queries offered at once),
+    then open-loop Poisson arrivals at 0.5x and 0.9x of the saturation rate;
+    one launch per query (the single-query entry points, sequentially) on the
+    first n_single queries of the same stream."""
+    import fzinputs
+    golden = fzinputs.load_golden()
+    counts = golden["served"]["counts"]
+    stream = fzinputs.served_stream(golden)
+    # every store query's output buffer (|Z| rows) is allocated up front
+    for i, q in enumerate(stream):
+        if q["mode"] == "store":
+            q["out"] = torch.empty((max(counts[i], 1), len(q["g"])), dtype=torch.int32,
+                                   device="cuda")
+            q["max_tuples"] = counts[i]
+    torch.cuda.synchronize()
+
+    def check(results, label):
+        for i, (q, r) in enumerate(zip(stream, results)):
+            ok = r["status"] == 0 and (r["count"] == counts[i] or
+                                       (q["mode"] == "exists" and r["found"]))
+            if q["mode"] == "store":
+                ok = r["status"] == 0 and r["total"] == counts[i] == r["written"]
+            if not ok:
+                raise RuntimeError(f"served ({label}): wrong result for query {i} {q}: {r}")
+
+    _serve(fz, stream[:500])  # warm-up: buffers of the slots
+    elapsed, st, res = _serve(fz, stream)
+    check(res, "saturation")
+    qps = len(stream) / elapsed
+    log(f"served saturation: {qps:.0f} queries/s, p50 {st['p50_us']:.0f} us, "
+        f"p99 {st['p99_us']:.0f} us")
+    out = {"queries": len(stream), "store_queries": golden["served"]["n_store"],
+           "saturation": {"queries_per_s": qps, "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                          "mean_batch": st["mean_batch"], "launches": st["launches"]}}
+    for frac in (0.5, 0.9):
+        gaps = fzinputs.exponential_gaps(11, frac * qps, len(stream))
+        el, st, res = _serve(fz, stream, gaps=gaps)
+        check(res, f"open loop {frac}")
+        out[f"open_loop_{frac}"] = {"offered_qps": frac * qps, "achieved_qps": len(stream) / el,
+                                    "p50_us": st["p50_us"], "p99_us": st["p99_us"],
+                                    "max_us": st["max_us"], "mean_batch": st["mean_batch"]}
+        log(f"served open loop at {frac} x: p50 {st['p50_us']:.0f} us, p99 {st['p99_us']:.0f} us")
+    # one launch per query
+    lat = []
+    t0 = time.perf_counter()
+    for i, q in enumerate(stream[:n_single]):
+        t1 = time.perf_counter()
+        if q["mode"] == "count":
+            c = fz.count(q["n"], q["g"])
+        elif q["mode"] == "hist":
+            c = int(fz.length_hist(q["n"], q["g"])[0].sum())
+        elif q["mode"] == "exists":
+            fz.exists(q["n"], q["g"], q["target_len"])
+            c = counts[i]  # the predicate reports no count
+        else:
+            c, _ = fz.enumerate_device(q["n"], q["g"], q["out"])
+        lat.append(time.perf_counter() - t1)
+        if c != counts[i]:
+            raise RuntimeError(f"one launch per query: wrong count for query {i}")
+    single_qps = n_single / (time.perf_counter() - t0)
+    log(f"one launch per query: {single_qps:.0f} queries/s")
+    out["one_launch_per_query"] = {"queries": n_single, "queries_per_s": single_qps,
+                                   "p50_us": percentile(lat, 0.5) * 1e6,
+                                   "p99_us": percentile(lat, 0.99) * 1e6}
+    out["speedup_vs_one_launch_per_query"] = qps / single_qps
+    out["workload"] = ("20000 queries drawn as the batch, 20% store queries (|Z| <= 1e7, "
+                       "written to device buffers allocated before timing), up to 4 launches "
+                       "in flight")
+    for q in stream:
+        q.pop("out", None)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB device to device 3 times (the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -209,6 +371,12 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
         log("copy calibration done (3 x 1 GiB)")
+    if not args.no_batch:
+        log("batch (4096 queries) ...")
+        res["batch"] = measure_batch(fz)
+    if not args.no_served:
+        log("served stream (20000 queries) ...")
+        res["served"] = measure_served(fz, torch)
     tr = measured_traffic()
     if tr:
         res["roofline"]["traffic"] = tr.get("count_walker_bytes")
