@@ -123,7 +123,7 @@ def measure_batch(fz, reps=3):
         res = fz.batch(qs)
         times.append(time.perf_counter() - t0)
         fz.profile_enable(False)
-        prep.append(fz.profile_read("batch.prep")[0])
+        prep.append(fz.profile_read("batch.tables")[0] + fz.profile_read("batch.slices")[0])
         walk.append(fz.profile_read("batch.walk")[0])
         for q, x, ww in zip(qs, res, w):
             ok = x["status"] == 0 and (x["count"] == ww["count"] or

@@ -217,12 +217,16 @@ int fz_last_stats(fz_stats *out);
 /* Per-slice record of the last successful enumeration on this device: the
  * elements and rows of each slice and the device wall clock (100 MHz ticks)
  * when a wavefront took it and finished it; for judging the balance of the
- * slice cut.  Copies min(cap, slices) records, *n_slices = slices. */
+ * slice cut.  After fz_batch, the records are the batch's work items, in
+ * the order of its work queue.  Copies min(cap, slices)
+ * records, *n_slices = slices. */
 typedef struct {
     uint64_t elements;
     uint64_t rows;
     uint64_t t_begin;
     uint64_t t_end;
+    uint32_t query;     /* fz_batch: index of the query the slice belongs to */
+    uint32_t slice;     /* fz_batch: slice index within that query */
 } fz_slice_info;
 int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
 
@@ -256,8 +260,8 @@ int fz_autotune(const fz_query *q, uint32_t nq, uint32_t reps, fz_tune_result *o
  * starts recording (it adds no synchronization of its own); fz_profile_read
  * gives the summed milliseconds and launch count of one kernel ("dp",
  * "restab", "slices", "enum.count", "enum.hist", "enum.exists", "enum.store",
- * "finalize", "unrank"; for fz_batch "batch.prep" (tables, residues and
- * slice bounds of all queries), "batch.walk", "batch.finalize") since the
+ * "finalize", "unrank"; for fz_batch "batch.tables" (count and work tables,
+ * residue tables), "batch.slices" (slice bounds), "batch.walk") since the
  * last reset. */
 int fz_profile_enable(int on);
 int fz_profile_reset(void);

@@ -52,7 +52,8 @@ class fz_stats(ctypes.Structure):
 
 class fz_slice_info(ctypes.Structure):
     _fields_ = [("elements", ctypes.c_uint64), ("rows", ctypes.c_uint64),
-                ("t_begin", ctypes.c_uint64), ("t_end", ctypes.c_uint64)]
+                ("t_begin", ctypes.c_uint64), ("t_end", ctypes.c_uint64),
+                ("query", ctypes.c_uint32), ("slice", ctypes.c_uint32)]
 
 
 class fz_query(ctypes.Structure):

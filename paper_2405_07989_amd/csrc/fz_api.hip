@@ -36,6 +36,10 @@ constexpr double kWorkRow = 50.0 * 64;
 constexpr double kWorkChunk = 23.0 * 64;
 constexpr double kWorkTrip = 7.0 * 64;
 constexpr double kWorkElem[4] = {4, 8, 5, 40}; // count, hist, exists, store
+// A skipped row costs about 1/2 instruction: 64 siblings per ballot scan.
+constexpr uint32_t kWorkSkip = 32;
+// Rows are skipped when the set has fewer elements than this per row.
+constexpr double kPruneElementsPerRow = 64.0;
 
 struct Ctx {
     bool ready = false;
@@ -45,6 +49,7 @@ struct Ctx {
     FzCtl *host_ctl = nullptr; // pinned
     DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out;
     BatchSlot batch; // fz_batch
+    bool last_batch = false; // fz_last_slices reads the batch's items
     fz_stats last{};
 };
 
@@ -55,6 +60,9 @@ uint32_t g_wg_per_cu = 0;
 uint32_t g_work_row = 0;
 uint32_t g_work_chunk = 0;
 uint32_t g_work_elem = 0;
+uint32_t g_prune_mode = 0; // 0: by the set's density, 1: always, 2: never
+
+bool worth_pruning(const FzPlan &P);
 
 struct ProfEntry {
     double ms = 0;
@@ -230,6 +238,8 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
     P->w_chunk = g_work_chunk ? g_work_chunk : (uint32_t)(wchunk + 0.5);
     P->w_el = g_work_elem ? g_work_elem : (uint32_t)kWorkElem[mode & 3];
     P->restab_in_lds = (size_t)2 * P->B * sizeof(int2) <= kLdsRestabBudget;
+    P->prune = 0;
+    P->w_skip = kWorkSkip;
     P->nbins = (uint32_t)(n / ming + 1);
     P->stride = (uint32_t)n + 1;
     P->target_len = 0;
@@ -287,6 +297,8 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
     P.hist_in_lds = (P.mode == FZM_HIST) &&
                     ((size_t)(FZK_WG / FZK_WAVE) * P.nbins * 8 <= kLdsHistBudget);
+    P.prune = (g_prune_mode == 1 || (g_prune_mode == 0 && worth_pruning(P))) ? 1 : 0;
+    if (P.d < 4) P.prune = 0;
     const uint64_t table_words = (uint64_t)(P.d - 1) * P.stride;
     const uint64_t cost_words = (uint64_t)(P.d - 2) * P.stride;
     FZ_TRY(ensure(c.S, table_words * 8));
@@ -331,6 +343,7 @@ int run_query(Ctx &c, FzPlan &P, FzBufs &B, const Launch &L, hipStream_t s)
     if (h.status & FZS_OVERFLOW) return FZ_EOVERFLOW;
     if (h.status & FZS_MISMATCH) return FZ_EINTERNAL;
     c.last.slices = P.n_slices;
+    c.last_batch = false;
     c.last.rows = h.rows;
     c.last.prefixes = h.prefixes;
     c.last.elements = h.count;
@@ -401,11 +414,11 @@ int do_enumerate(uint64_t n, const uint32_t *g, uint32_t d, uint32_t *out, bool 
     return wr < N ? FZ_TRUNCATED : FZ_OK;
 }
 
-// Rough work of a query in the walker's units (row, chunk and element
-// weights of its plan), from the leading terms of the counts of rows, lane
-// prefixes and elements: a set {a : sum_{i<k} a_i g_i <= v} has about
-// v^k / (k! prod g_i) points.  Only used to decide how finely to cut.
-double estimate_work(const FzPlan &P)
+// Rough counts of a query's rows (a_1..a_{d-3}), lane prefixes
+// (a_1..a_{d-2}) and elements, from the leading terms: a set
+// {a : sum_{i<k} a_i g_i <= v} has about v^k / (k! prod g_i) points.  Only
+// used to decide how finely to cut and whether to skip empty rows.
+void estimate_counts(const FzPlan &P, double *rows, double *pref, double *el)
 {
     const uint32_t M = P.d - 3;
     const double ln1 = std::log((double)P.n + 1.0);
@@ -416,11 +429,31 @@ double estimate_work(const FzPlan &P)
     lg_rows += M * ln1 - std::lgamma(M + 1.0);
     lg_pref += (M + 1) * ln1 - std::lgamma(M + 2.0);
     lg_el += (M + 2) * ln1 - std::lgamma(M + 3.0);
-    const double rows = std::exp(std::min(lg_rows, 200.0));
-    const double pref = std::exp(std::min(lg_pref, 200.0));
-    const double el = std::exp(std::min(lg_el, 200.0));
-    return P.w_row * std::max(rows, 1.0) + P.w_chunk * (pref / FZK_WAVE + std::max(rows, 1.0)) +
-           P.w_el * el;
+    *rows = std::max(std::exp(std::min(lg_rows, 200.0)), 1.0);
+    *pref = std::exp(std::min(lg_pref, 200.0));
+    *el = std::exp(std::min(lg_el, 200.0));
+}
+
+// Sparse sets (few elements per row) walk only the rows that have elements:
+// most rows then have none, and skipping them costs a fraction of a walk.
+bool worth_pruning(const FzPlan &P)
+{
+    if (P.d < 4) return false;
+    double rows, pref, el;
+    estimate_counts(P, &rows, &pref, &el);
+    return el < kPruneElementsPerRow * rows;
+}
+
+// Rough work of a query in the walker's units.  With pruning, each element
+// is charged a row and a chunk of its own (an upper bound for a sparse set)
+// and every row the cost of being skipped.
+double estimate_work(const FzPlan &P)
+{
+    double rows, pref, el;
+    estimate_counts(P, &rows, &pref, &el);
+    if (P.prune)
+        return P.w_skip * rows + (double)(P.w_row + P.w_chunk + P.w_el) * el;
+    return P.w_row * rows + P.w_chunk * (pref / FZK_WAVE + rows) + P.w_el * el;
 }
 
 void current_knobs(uint32_t *spw, uint32_t *wgcu)
@@ -448,19 +481,33 @@ hipError_t ensure_pinned(void **p, size_t *cap, size_t bytes)
 
 void BatchSlot::release()
 {
-    for (DevBuf *b : {&meta, &tables, &restabs, &bounds, &base, &recs, &bins, &res, &cursor}) {
+    for (DevBuf *b :
+         {&meta, &tables, &restabs, &bounds, &base, &recs, &bins, &res, &cursor, &totals}) {
         if (b->p) (void)hipFree(b->p);
         b->p = nullptr;
         b->cap = 0;
     }
-    for (void **h : {(void **)&h_meta, (void **)&h_res, (void **)&h_done, (void **)&h_bins}) {
+    for (void **h : {(void **)&h_meta, (void **)&h_res, (void **)&h_done, (void **)&h_bins,
+                     (void **)&h_totals}) {
         if (*h) (void)hipHostFree(*h);
         *h = nullptr;
     }
     h_meta_cap = 0;
     h_cap = 0;
     h_bins_cap = 0;
+    h_totals_cap = 0;
 }
+
+// Work weights of the batch walker, in its own units (1/8 of the time of an
+// element step of a long run), fitted to per-query wave time over the mixed
+// 4096-query workload: a row about 110 element steps, a row visited while
+// skipping empty rows about 300 (its emptiness test is a dependent load), a
+// 64-lane chunk about 37, a skipped row about 8.
+constexpr uint32_t kBatchRow = 880, kBatchRowSkipping = 2370, kBatchChunk = 300,
+                   kBatchSkip = 62;
+constexpr uint32_t kBatchElem[4] = {35, 40, 40, 48}; // count, hist, exists, store
+// Skipping pays off only on sets with enough rows.
+constexpr double kPruneMinRows = 4096.0;
 
 int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
                  uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile)
@@ -470,8 +517,9 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
     Q.assign(nq, FzBatchQuery{});
     S.qst.assign(nq, FZ_OK);
     S.nq = nq;
+    S.n_items = 0;
     std::vector<double> work(nq, 0.0);
-    double total_work = 0;
+    double est_total = 0;
     uint32_t maxm = 0, max_du = 0, bstride = 1;
     bool any_hist = false;
     for (uint32_t i = 0; i < nq; ++i) {
@@ -490,33 +538,37 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
         P.target_len = q.target_len;
         if (q.mode == FZ_MODE_STORE) P.max_tuples = q.max_tuples;
         Q[i].max_total = store_cap;
+        double rows, pref, el;
+        estimate_counts(P, &rows, &pref, &el);
+        P.prune = (P.d >= 4 && (g_prune_mode == 1 ||
+                                (g_prune_mode == 0 && worth_pruning(P) && rows >= kPruneMinRows)))
+                      ? 1 : 0;
+        P.w_row = g_work_row ? g_work_row : (P.prune ? kBatchRowSkipping : kBatchRow);
+        P.w_chunk = g_work_chunk ? g_work_chunk : kBatchChunk;
+        P.w_el = g_work_elem ? g_work_elem : kBatchElem[P.mode & 3];
+        P.w_skip = kBatchSkip;
         work[i] = estimate_work(P);
-        total_work += work[i];
+        est_total += work[i];
         maxm = std::max(maxm, P.d - 3);
         bstride = std::max(bstride, P.d - 2);
         if (q.mode == FZ_MODE_STORE) max_du = std::max(max_du, P.d_user);
         if (q.mode == FZ_MODE_HIST) any_hist = true;
     }
-    const double waves = (double)cus * wgcu * (FZK_WG / FZK_WAVE);
-    const double target = std::max(total_work / (waves * spw), 1.0);
+    const double slots = (double)cus * wgcu * (FZK_WG / FZK_WAVE) * spw;
     const uint32_t lds_bins = any_hist ? kBatchLdsBins : 0;
 
-    // cut: a query worth more than two target slices gets count and work
-    // tables and W_q slices; stores always get tables (their rows are placed
-    // by rank).  Items of large queries first, then the rest by falling work.
-    std::vector<uint32_t> order;
-    for (uint32_t i = 0; i < nq; ++i)
-        if (Q[i].plan.d) order.push_back(i);
+    // Phase 1: count and work tables for every query that may be cut --
+    // stores (rows placed by rank), sparse queries (they skip empty rows by
+    // the count table) and any query estimated above half a slice -- and the
+    // exact modelled work of each, read back to size its slice count.
+    std::vector<uint32_t> tabled;
     uint64_t tab_words = 0, res_words = 0, bin_words = 0;
-    uint32_t n_items = 0, n_bounds = 0;
-    std::vector<uint32_t> sliced_ids;
-    for (uint32_t i : order) {
+    const double est_target = std::max(est_total / slots, 1.0);
+    for (uint32_t i = 0; i < nq; ++i) {
         FzBatchQuery &B = Q[i];
         FzPlan &P = B.plan;
-        const double w = work[i] / target;
-        B.sliced = (P.mode == FZM_STORE || w > 2.0) ? 1 : 0;
-        B.n_slices = B.sliced ? (uint32_t)std::min(std::max(std::ceil(w), 1.0), 65536.0) : 1;
-        P.n_slices = B.n_slices;
+        if (!P.d) continue;
+        B.sliced = (P.mode == FZM_STORE || P.prune || work[i] > 0.5 * est_target) ? 1 : 0;
         P.hist_in_lds = P.mode == FZM_HIST && P.nbins <= lds_bins;
         P.restab_in_lds = 0;
         if (B.sliced) {
@@ -524,7 +576,7 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
             tab_words += (uint64_t)(P.d - 1) * P.stride;
             B.c_off = tab_words;
             tab_words += (uint64_t)(P.d - 2) * P.stride;
-            sliced_ids.push_back(i);
+            tabled.push_back(i);
         }
         B.tab_off = res_words;
         res_words += 2 * (uint64_t)P.B;
@@ -533,27 +585,15 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
             bin_words += P.nbins;
         }
         B.out = qs[i].d_out;
-        B.bound_off = n_bounds;
-        n_bounds += B.n_slices + 1;
     }
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        if (Q[a].sliced != Q[b].sliced) return Q[a].sliced > Q[b].sliced;
-        return work[a] / Q[a].n_slices > work[b] / Q[b].n_slices;
-    });
-    for (uint32_t i : order) {
-        Q[i].item_off = n_items;
-        n_items += Q[i].n_slices;
-    }
-    S.n_items = n_items;
-
-    // pinned staging: queries, boundary jobs, items, ids of sliced queries
+    const uint32_t n_tab = (uint32_t)tabled.size();
     auto up = [](size_t o) { return (o + 63) & ~(size_t)63; };
     const size_t o_q = 0;
-    const size_t o_jobs = up(o_q + (size_t)nq * sizeof(FzBatchQuery));
-    const size_t o_items = up(o_jobs + (size_t)n_bounds * sizeof(FzBatchJob));
-    const size_t o_ids = up(o_items + (size_t)n_items * sizeof(FzBatchJob));
-    const size_t meta_bytes = up(o_ids + sliced_ids.size() * 4);
-    FZ_TRY(ensure_pinned((void **)&S.h_meta, &S.h_meta_cap, meta_bytes));
+    const size_t o_ids = up(o_q + (size_t)nq * sizeof(FzBatchQuery));
+    const size_t meta1 = up(o_ids + (size_t)n_tab * 4);
+    FZ_TRY(ensure_pinned((void **)&S.h_meta, &S.h_meta_cap, meta1));
+    std::memcpy(S.h_meta + o_q, Q.data(), (size_t)nq * sizeof(FzBatchQuery));
+    if (n_tab) std::memcpy(S.h_meta + o_ids, tabled.data(), (size_t)n_tab * 4);
     if (S.h_cap < nq) {
         size_t c1 = 0, c2 = 0;
         if (S.h_res) (void)hipHostFree(S.h_res);
@@ -569,7 +609,88 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
         size_t cap = S.h_bins_cap * 8;
         FZ_TRY(ensure_pinned((void **)&S.h_bins, &cap, std::max<size_t>(bin_words, 1) * 8));
         S.h_bins_cap = cap / 8;
+        cap = S.h_totals_cap * 8;
+        FZ_TRY(ensure_pinned((void **)&S.h_totals, &cap, std::max<size_t>(n_tab, 1) * 8));
+        S.h_totals_cap = cap / 8;
     }
+    std::memset(S.h_done, 0, (size_t)nq * 4);
+    std::memset(S.h_res, 0, (size_t)nq * sizeof(FzBatchResult));
+    FZ_TRY(ensure(S.meta, meta1));
+    FZ_TRY(ensure(S.tables, tab_words * 8));
+    FZ_TRY(ensure(S.restabs, res_words * sizeof(int2)));
+    FZ_TRY(ensure(S.bins, bin_words * 8));
+    FZ_TRY(ensure(S.res, (size_t)nq * sizeof(FzBatchResult)));
+    FZ_TRY(ensure(S.totals, (size_t)std::max(n_tab, 1u) * 8));
+    FZ_TRY(ensure(S.cursor, 256));
+    uint8_t *meta = (uint8_t *)S.meta.p;
+
+    FzBatchBufs B;
+    std::memset(&B, 0, sizeof B);
+    B.queries = (const FzBatchQuery *)(meta + o_q);
+    B.tables = (uint64_t *)S.tables.p;
+    B.restabs = (int2 *)S.restabs.p;
+    B.bins = (uint64_t *)S.bins.p;
+    B.res = (FzBatchResult *)S.res.p;
+    B.totals = (uint64_t *)S.totals.p;
+    B.cursor = (uint32_t *)S.cursor.p;
+    B.host_res = S.h_res;
+    B.host_bins = S.h_bins;
+    B.host_done = S.h_done;
+    B.nq = nq;
+    B.n_bins = bin_words;
+    bool any_valid = false;
+    for (uint32_t i = 0; i < nq; ++i) any_valid = any_valid || Q[i].plan.d != 0;
+    if (!any_valid) return FZ_OK; // every query was rejected on the host
+    FZ_TRY(hipMemcpyAsync(meta, S.h_meta, meta1, hipMemcpyHostToDevice, st));
+    const uint32_t *ids = (const uint32_t *)(meta + o_ids);
+    if (profile) FZ_LAUNCH("batch.tables", st, fzk_launch_batch_tables(B, n_tab, ids, st));
+    else FZ_TRY(fzk_launch_batch_tables(B, n_tab, ids, st));
+    if (n_tab)
+        FZ_TRY(hipMemcpyAsync(S.h_totals, S.totals.p, (size_t)n_tab * 8, hipMemcpyDeviceToHost,
+                              st));
+    // phase 2 restages the query array (host and device copies may move)
+    FZ_TRY(hipStreamSynchronize(st));
+
+    // Phase 2: cut.  A query with tables gets ceil(work / target) slices of
+    // its exact modelled work; the others are one slice each.  Items of large
+    // queries first, then the rest by falling work per slice.
+    std::vector<double> exact(nq, 0.0);
+    double total = 0;
+    for (uint32_t k = 0; k < n_tab; ++k) {
+        const uint64_t c = S.h_totals[k];
+        exact[tabled[k]] = c == ~0ull ? 0.0 : (double)c; // overflow: walked not at all
+    }
+    for (uint32_t i = 0; i < nq; ++i)
+        if (Q[i].plan.d) total += Q[i].sliced ? exact[i] : work[i];
+    const double target = std::max(total / slots, 1.0);
+    std::vector<uint32_t> order;
+    uint32_t n_items = 0, n_bounds = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+        FzBatchQuery &B2 = Q[i];
+        if (!B2.plan.d) continue;
+        if (B2.sliced) work[i] = exact[i];
+        B2.n_slices = B2.sliced
+                          ? (uint32_t)std::min(std::max(std::ceil(work[i] / target), 1.0), 65536.0)
+                          : 1;
+        B2.plan.n_slices = B2.n_slices;
+        B2.bound_off = n_bounds;
+        n_bounds += B2.n_slices + 1;
+        order.push_back(i);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
+        if (Q[a].sliced != Q[b].sliced) return Q[a].sliced > Q[b].sliced;
+        return work[a] / Q[a].n_slices > work[b] / Q[b].n_slices;
+    });
+    for (uint32_t i : order) {
+        Q[i].item_off = n_items;
+        n_items += Q[i].n_slices;
+    }
+    S.n_items = n_items;
+
+    const size_t o_jobs = up(o_q + (size_t)nq * sizeof(FzBatchQuery));
+    const size_t o_items = up(o_jobs + (size_t)n_bounds * sizeof(FzBatchJob));
+    const size_t meta2 = up(o_items + (size_t)n_items * sizeof(FzBatchJob));
+    FZ_TRY(ensure_pinned((void **)&S.h_meta, &S.h_meta_cap, meta2));
     uint8_t *hm = S.h_meta;
     std::memcpy(hm + o_q, Q.data(), (size_t)nq * sizeof(FzBatchQuery));
     FzBatchJob *hj = (FzBatchJob *)(hm + o_jobs);
@@ -578,53 +699,28 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
         for (uint32_t j = 0; j <= Q[i].n_slices; ++j) hj[Q[i].bound_off + j] = {i, j};
         for (uint32_t j = 0; j < Q[i].n_slices; ++j) hi[Q[i].item_off + j] = {i, j};
     }
-    if (!sliced_ids.empty())
-        std::memcpy(hm + o_ids, sliced_ids.data(), sliced_ids.size() * 4);
-    std::memset(S.h_done, 0, (size_t)nq * 4);
-    std::memset(S.h_res, 0, (size_t)nq * sizeof(FzBatchResult));
-
-    FZ_TRY(ensure(S.meta, meta_bytes));
-    FZ_TRY(ensure(S.tables, tab_words * 8));
-    FZ_TRY(ensure(S.restabs, res_words * sizeof(int2)));
+    FZ_TRY(ensure(S.meta, meta2));
     FZ_TRY(ensure(S.bounds, (size_t)n_bounds * bstride * 4));
     FZ_TRY(ensure(S.base, (size_t)n_bounds * 8));
     FZ_TRY(ensure(S.recs, (size_t)std::max(n_items, 1u) * sizeof(FzSliceRec)));
-    FZ_TRY(ensure(S.bins, bin_words * 8));
-    FZ_TRY(ensure(S.res, (size_t)nq * sizeof(FzBatchResult)));
-    FZ_TRY(ensure(S.cursor, 256));
-    uint8_t *meta = (uint8_t *)S.meta.p;
-    FZ_TRY(hipMemcpyAsync(meta, hm, meta_bytes, hipMemcpyHostToDevice, st));
-
-    FzBatchBufs B;
+    meta = (uint8_t *)S.meta.p; // a larger staging area moves the device copy
+    FZ_TRY(hipMemcpyAsync(meta, hm, meta2, hipMemcpyHostToDevice, st));
     B.queries = (const FzBatchQuery *)(meta + o_q);
     B.bjobs = (const FzBatchJob *)(meta + o_jobs);
     B.items = (const FzBatchJob *)(meta + o_items);
-    B.tables = (uint64_t *)S.tables.p;
-    B.restabs = (int2 *)S.restabs.p;
     B.bounds = (uint32_t *)S.bounds.p;
     B.base = (uint64_t *)S.base.p;
     B.recs = (FzSliceRec *)S.recs.p;
-    B.bins = (uint64_t *)S.bins.p;
-    B.res = (FzBatchResult *)S.res.p;
-    B.cursor = (uint32_t *)S.cursor.p;
-    B.host_res = S.h_res;
-    B.host_bins = S.h_bins;
-    B.host_done = S.h_done;
-    B.nq = nq;
     B.n_bjobs = n_bounds;
     B.n_items = n_items;
     B.bstride = bstride;
-    B.n_bins = bin_words;
-    if (n_items == 0) return FZ_OK; // every query was rejected on the host
     const uint32_t nwg = (uint32_t)std::min<uint64_t>((uint64_t)cus * wgcu,
                                                       std::max<uint32_t>(1, (n_items + 3) / 4));
-    const uint32_t *ids = (const uint32_t *)(meta + o_ids);
-    const uint32_t n_sliced = (uint32_t)sliced_ids.size();
     if (profile) {
-        FZ_LAUNCH("batch.prep", st, fzk_launch_batch_prep(B, n_sliced, ids, st));
+        FZ_LAUNCH("batch.slices", st, fzk_launch_batch_slices(B, st));
         FZ_LAUNCH("batch.walk", st, fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
     } else {
-        FZ_TRY(fzk_launch_batch_prep(B, n_sliced, ids, st));
+        FZ_TRY(fzk_launch_batch_slices(B, st));
         FZ_TRY(fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
     }
     return FZ_OK;
@@ -693,6 +789,7 @@ int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
     prof_collect();
     for (uint32_t i = 0; i < nq; ++i) batch_result(c.batch, qs[i], i, &rs[i]);
     c.last.slices = c.batch.n_items;
+    c.last_batch = true;
     return FZ_OK;
 }
 
@@ -844,12 +941,26 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices)
     const uint32_t k = std::min(n, cap);
     if (k == 0) return FZ_OK;
     std::vector<FzSliceRec> tmp(k);
-    FZ_TRY(hipMemcpy(tmp.data(), c->recs.p, k * sizeof(FzSliceRec), hipMemcpyDeviceToHost));
+    const void *src = c->last_batch ? c->batch.recs.p : c->recs.p;
+    FZ_TRY(hipMemcpy(tmp.data(), src, k * sizeof(FzSliceRec), hipMemcpyDeviceToHost));
+    // a batch's items: (query, slice) from the staged item list
+    std::vector<FzBatchJob> items;
+    if (c->last_batch) {
+        items.assign(k, FzBatchJob{0, 0});
+        for (uint32_t q = 0; q < c->batch.nq; ++q) {
+            const FzBatchQuery &B = c->batch.Q[q];
+            if (!B.plan.d) continue;
+            for (uint32_t j = 0; j < B.n_slices; ++j)
+                if (B.item_off + j < k) items[B.item_off + j] = {q, j};
+        }
+    }
     for (uint32_t i = 0; i < k; ++i) {
         out[i].elements = tmp[i].elements;
         out[i].rows = tmp[i].rows;
         out[i].t_begin = tmp[i].t_begin;
         out[i].t_end = tmp[i].t_end;
+        out[i].query = c->last_batch ? items[i].q : 0;
+        out[i].slice = c->last_batch ? items[i].j : i;
     }
     return FZ_OK;
 }
@@ -863,6 +974,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "work_row") == 0) g_work_row = (uint32_t)value;
     else if (std::strcmp(key, "work_chunk") == 0) g_work_chunk = (uint32_t)value;
     else if (std::strcmp(key, "work_element") == 0) g_work_elem = (uint32_t)value;
+    else if (std::strcmp(key, "skip_empty_rows") == 0 && value <= 2) g_prune_mode = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

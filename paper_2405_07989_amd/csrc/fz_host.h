@@ -33,7 +33,9 @@ extern std::mutex g_mu;
 // and the plan of the batch last launched from it.  fz_batch uses one per
 // device; a server owns one per launch slot.
 struct BatchSlot {
-    DevBuf meta, tables, restabs, bounds, base, recs, bins, res, cursor;
+    DevBuf meta, tables, restabs, bounds, base, recs, bins, res, cursor, totals;
+    uint64_t *h_totals = nullptr; // pinned: C[0][n] of the queries with tables
+    size_t h_totals_cap = 0;
     uint8_t *h_meta = nullptr;   // pinned staging of queries, jobs and items
     size_t h_meta_cap = 0;
     FzBatchResult *h_res = nullptr;

@@ -51,6 +51,8 @@ struct FzPlan {
     uint32_t restab_in_lds;
     uint32_t nbins;      // histogram bins (n / min g + 1)
     uint32_t hist_in_lds;
+    uint32_t prune;      // skip rows whose subtree is empty (sparse sets; needs S)
+    uint32_t w_skip;     // slice-cut weight of a skipped (empty) row
     uint32_t n_slices;   // W
     uint32_t stride;     // n + 1: row length of the count table
     uint64_t target_len; // predicate target
@@ -147,6 +149,7 @@ struct FzBatchBufs {
     FzSliceRec *recs;          // per item
     uint64_t *bins;            // histogram bins of hist queries
     FzBatchResult *res;        // per query
+    uint64_t *totals;          // C[0][n] of each query with tables (ids order)
     uint32_t *cursor;          // walker item cursor (own 128-byte line)
     // optional host-visible copies (pinned, coherent): a finished query's
     // result and bins are written there and host_done[q] is set to 1 with a
@@ -168,9 +171,11 @@ hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, h
 hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *ranks,
                              uint64_t nranks, uint32_t *out, hipStream_t s);
 size_t fzk_enum_lds_bytes(const FzPlan &p);
-// batch: zeroing, count / work tables, residue tables and slice bounds; then
-// the persistent walker, which also finishes each query
-hipError_t fzk_launch_batch_prep(const FzBatchBufs &b, uint32_t n_sliced,
-                                 const uint32_t *sliced_ids, hipStream_t s);
+// batch: zeroing, count / work tables (and their totals) and residue tables;
+// then, once the host has cut the queries, slice bounds; then the persistent
+// walker, which also finishes each query
+hipError_t fzk_launch_batch_tables(const FzBatchBufs &b, uint32_t n_tabled,
+                                   const uint32_t *tabled_ids, hipStream_t s);
+hipError_t fzk_launch_batch_slices(const FzBatchBufs &b, hipStream_t s);
 hipError_t fzk_launch_batch_walk(const FzBatchBufs &b, uint32_t maxm, uint32_t nwg,
                                  uint32_t lds_bins, uint32_t max_du, hipStream_t s);

@@ -118,6 +118,7 @@ __device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM
                                              uint32_t t)
 {
     if (t == 0) return 0;
+    if (P.prune && SM[v] == 0) return P.w_skip; // an empty row is skipped, not walked
     const uint64_t el = SM[v] - (t * (uint64_t)P.G2 <= v ? SM[v - t * P.G2] : 0);
     const uint64_t chunks = (t + FZK_WAVE - 1) / FZK_WAVE;
     uint64_t w = P.w_row + chunks * P.w_chunk;
@@ -362,6 +363,7 @@ struct WalkIO {
     uint32_t *out;      // store destination, row-major [.][d_user]
     uint64_t *s_incl;   // store scratch of this wave: scan, t0, ad0, rows
     uint32_t *s_t0, *s_ad0, *s_stage;
+    const uint64_t *S;  // count table, for skipping empty subtrees (P.prune)
 };
 
 struct WalkOut {
@@ -393,7 +395,86 @@ __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint
     }
 }
 
-template <int MAXM, int MODE, bool TLDS>
+// Moves the row odometer a[0..M-1] (remainders rr) to the first row, at or
+// after the current one and not past the end prefix e, whose every level has
+// a completion: S[k+1][rr[k+1]] > 0 for all k < M.  An empty subtree is
+// skipped as a whole: the wave tests 64 siblings at once (lane i takes
+// a[k] + i) and jumps to the first non-empty one, or moves on to the next
+// prefix of a shallower level when none is left.  Levels < chk are known to
+// be non-empty.  Returns false when the slice has no such row left.
+template <int MAXM>
+__device__ __forceinline__ bool skip_empty(const FzPlan &P, const uint32_t M, const uint64_t *S,
+                                           uint32_t *a, uint32_t *rr, const uint32_t *e,
+                                           bool end_open, int &chk, bool &moved, uint32_t lane)
+{
+    auto advance = [&](int kk, uint32_t j) {
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            if (k == kk) {
+                a[k] += j;
+                rr[k + 1] -= j * P.g[k];
+            } else if (k > kk) {
+                a[k] = 0;
+                rr[k + 1] = rr[k];
+            }
+        }
+    };
+    for (;;) {
+        int kz = -1;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k)
+            if (k < (int)M && k >= chk && kz < 0) {
+                const uint64_t c = S[(uint64_t)(k + 1) * P.stride + rr[k + 1]];
+                if ((uni((uint32_t)c) | uni((uint32_t)(c >> 32))) == 0) kz = k;
+            }
+        if (kz < 0) {
+            chk = (int)M;
+            return true;
+        }
+        moved = true;
+        bool pe = !end_open; // a[0..kz-1] is the end prefix's: a[kz] <= e[kz]
+        uint32_t gk = 0, ak = 0, rk = 0, ek = 0;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            if (k < kz) pe = pe && a[k] == e[k];
+            if (k == kz) {
+                gk = P.g[k];
+                ak = a[k];
+                rk = rr[k + 1];
+                ek = e[k];
+            }
+        }
+        const int64_t v = (int64_t)rk - (int64_t)lane * gk;
+        const bool in = v >= 0 && (!pe || ak + lane <= ek);
+        const bool nz = in && S[(uint64_t)(kz + 1) * P.stride + (uint64_t)v] != 0;
+        const uint64_t m = __ballot(nz);
+        if (m) {
+            advance(kz, (uint32_t)__builtin_ctzll(m));
+            chk = kz + 1;
+            continue;
+        }
+        // all 64 were empty: go on at a[kz] + 64 if that sibling exists (its
+        // remainder is >= 0 and, under the end prefix, it is <= e[kz])
+        const bool more = (int64_t)rk - (int64_t)FZK_WAVE * gk >= 0 && (!pe || ak + FZK_WAVE <= ek);
+        if (more) {
+            advance(kz, FZK_WAVE);
+            chk = kz;
+            continue;
+        }
+        if (pe) return false; // the end prefix bounds this level: nothing is left
+        // nothing under a[0..kz-1]: the next prefix of a shallower level (it
+        // cannot pass the end, which lies after this whole subtree)
+        int kk = -1;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k)
+            if (k < kz && rr[k + 1] >= P.g[k]) kk = k;
+        if (kk < 0) return false;
+        advance(kk, 1);
+        chk = kk;
+    }
+}
+
+template <int MAXM, int MODE, bool TLDS, bool PRUNE>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                                               const uint32_t *b0, const uint32_t *b1,
                                               uint64_t rank, const WalkIO &io, uint32_t lane)
@@ -442,8 +523,19 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
         uint32_t plen = 0;
 #pragma unroll
         for (int k = 0; k < MAXM; ++k) plen += a[k];
+        int chk = 0; // skip_empty: levels < chk known to have elements
         bool done = false;
         while (!done) {
+            if (PRUNE && M > 0) {
+                bool moved = false;
+                if (!skip_empty<MAXM>(P, M, io.S, a, rr, e, end_open, chk, moved, lane)) break;
+                if (moved) {
+                    xs = 0;
+                    plen = 0;
+#pragma unroll
+                    for (int k = 0; k < MAXM; ++k) plen += a[k];
+                }
+            }
             const uint32_t Rp = rr[MAXM];
             const int32_t xhi = (int32_t)fdiv(Rp, P.div_G2);
             bool last = !end_open;
@@ -606,6 +698,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
 #pragma unroll
             for (int k = 0; k < MAXM; ++k) plen += a[k];
             xs = 0;
+            chk = kk; // levels above kk kept their (non-empty) prefix
         }
     }
     WalkOut o;
@@ -618,7 +711,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
 // Single query.  Persistent workgroups of four waves; each wave takes slices
 // from an atomic cursor.
 // LDS: [residue table, 2B int2, when it fits][per-wave consumer scratch].
-template <int M, int MODE, bool TLDS>
+template <int M, int MODE, bool TLDS, bool PRUNE>
 __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -643,6 +736,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.gbins = Bf.hist;
     io.found = &Bf.ctl->found;
     io.out = Bf.out;
+    io.S = Bf.S;
     uint64_t *grow = nullptr;
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) {
@@ -675,7 +769,8 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         }
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
-        const WalkOut o = walk_slice<M, MODE, TLDS>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
+        const WalkOut o =
+            walk_slice<M, MODE, TLDS, PRUNE>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -822,6 +917,16 @@ __global__ void __launch_bounds__(1024) fz_batch_dp_kernel(FzBatchBufs B, const 
     const FzBatchQuery &Q = B.queries[ids[blockIdx.x]];
     const FzPlan P = Q.plan;
     dp_query(P, B.tables + Q.s_off, B.tables + Q.c_off, part);
+}
+
+// Total modelled work C[0][n] of each query with tables, for the host to
+// size its slice count.
+__global__ void fz_batch_totals_kernel(FzBatchBufs B, const uint32_t *ids, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const FzBatchQuery &Q = B.queries[ids[i]];
+    B.totals[i] = B.tables[Q.c_off + Q.plan.n];
 }
 
 __global__ void fz_batch_restab_kernel(FzBatchBufs B)
@@ -1023,20 +1128,26 @@ __global__ void __launch_bounds__(FZK_WG)
             io.found = &B.res[q].found;
             io.gbins = B.bins + Q.bins_off;
             io.out = Q.out;
+            io.S = B.tables + Q.s_off; // read only when P.prune (set for cut queries)
             io.wbins = nullptr;
             const bool lds_hist = mode == FZM_HIST && P.hist_in_lds;
             if (lds_hist) {
                 io.wbins = wb;
                 for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) wb[i] = 0;
             }
+            const bool prune = uni(P.prune) != 0;
             if (mode == FZM_COUNT)
-                o = walk_slice<MAXM, FZM_COUNT, false>(P, M, b0, b1, base, io, lane);
+                o = prune ? walk_slice<MAXM, FZM_COUNT, false, true>(P, M, b0, b1, base, io, lane)
+                          : walk_slice<MAXM, FZM_COUNT, false, false>(P, M, b0, b1, base, io, lane);
             else if (mode == FZM_HIST)
-                o = walk_slice<MAXM, FZM_HIST, false>(P, M, b0, b1, base, io, lane);
+                o = prune ? walk_slice<MAXM, FZM_HIST, false, true>(P, M, b0, b1, base, io, lane)
+                          : walk_slice<MAXM, FZM_HIST, false, false>(P, M, b0, b1, base, io, lane);
             else if (mode == FZM_EXISTS)
-                o = walk_slice<MAXM, FZM_EXISTS, false>(P, M, b0, b1, base, io, lane);
+                o = prune ? walk_slice<MAXM, FZM_EXISTS, false, true>(P, M, b0, b1, base, io, lane)
+                          : walk_slice<MAXM, FZM_EXISTS, false, false>(P, M, b0, b1, base, io, lane);
             else
-                o = walk_slice<MAXM, FZM_STORE, false>(P, M, b0, b1, base, io, lane);
+                o = prune ? walk_slice<MAXM, FZM_STORE, false, true>(P, M, b0, b1, base, io, lane)
+                          : walk_slice<MAXM, FZM_STORE, false, false>(P, M, b0, b1, base, io, lane);
             if (lds_hist) {
                 for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
                     const uint64_t h = wb[i];
@@ -1115,35 +1226,42 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
     return bytes;
 }
 
-template <int M, bool TLDS>
+template <int M, bool TLDS, bool PRUNE>
 static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
     const size_t lds = fzk_enum_lds_bytes(p);
     switch (p.mode) {
     case FZM_COUNT:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_COUNT, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
-                           p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_COUNT, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
+                           lds, s, p, b);
         break;
     case FZM_HIST:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
-                           p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
+                           lds, s, p, b);
         break;
     case FZM_EXISTS:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
-                           p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
+                           lds, s, p, b);
         break;
     default:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS>), dim3(nwg), dim3(FZK_WG), lds, s,
-                           p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
+                           lds, s, p, b);
         break;
     }
 }
 
+// Skipping empty rows needs at least one row coordinate (M >= 1).
 template <int M>
 static hipError_t launch_enum_m(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
-    if (p.restab_in_lds) launch_enum_mt<M, true>(p, b, nwg, s);
-    else launch_enum_mt<M, false>(p, b, nwg, s);
+    constexpr bool CAN_PRUNE = M > 0;
+    if (CAN_PRUNE && p.prune) {
+        if (p.restab_in_lds) launch_enum_mt<M, true, CAN_PRUNE>(p, b, nwg, s);
+        else launch_enum_mt<M, false, CAN_PRUNE>(p, b, nwg, s);
+    } else {
+        if (p.restab_in_lds) launch_enum_mt<M, true, false>(p, b, nwg, s);
+        else launch_enum_mt<M, false, false>(p, b, nwg, s);
+    }
     return hipGetLastError();
 }
 
@@ -1195,16 +1313,24 @@ static void launch_batch_enum(const FzBatchBufs &b, uint32_t nwg, uint32_t lds_b
                        lds_bins, max_du);
 }
 
-hipError_t fzk_launch_batch_prep(const FzBatchBufs &b, uint32_t n_sliced,
-                                 const uint32_t *sliced_ids, hipStream_t s)
+hipError_t fzk_launch_batch_tables(const FzBatchBufs &b, uint32_t n_tabled,
+                                   const uint32_t *tabled_ids, hipStream_t s)
 {
     hipLaunchKernelGGL(fz_zero_kernel, dim3(64), dim3(256), 0, s, (uint64_t *)b.res,
                        (uint64_t)b.nq * (sizeof(FzBatchResult) / 8));
     if (b.n_bins)
         hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.bins, b.n_bins);
-    if (n_sliced)
-        hipLaunchKernelGGL(fz_batch_dp_kernel, dim3(n_sliced), dim3(1024), 0, s, b, sliced_ids);
+    if (n_tabled) {
+        hipLaunchKernelGGL(fz_batch_dp_kernel, dim3(n_tabled), dim3(1024), 0, s, b, tabled_ids);
+        hipLaunchKernelGGL(fz_batch_totals_kernel, dim3((n_tabled + 255) / 256), dim3(256), 0, s,
+                           b, tabled_ids, n_tabled);
+    }
     hipLaunchKernelGGL(fz_batch_restab_kernel, dim3(b.nq), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t fzk_launch_batch_slices(const FzBatchBufs &b, hipStream_t s)
+{
     hipLaunchKernelGGL(fz_batch_slices_kernel, dim3((b.n_bjobs + 255) / 256), dim3(256), 0, s, b);
     return hipGetLastError();
 }

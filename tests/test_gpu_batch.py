@@ -151,3 +151,24 @@ def test_autotune_keeps_results(fz):
             assert a["count"] == b["count"], q
         if q["mode"] == "hist":
             assert np.array_equal(a["bins"], b["bins"])
+
+
+@pytest.mark.parametrize("mode", [1, 2], ids=["skip", "noskip"])
+def test_row_skipping_in_a_batch(fz, mode):
+    from test_gpu_parity import SPARSE
+    qs = []
+    for n, g in SPARSE:
+        for m in ("count", "hist", "exists", "store"):
+            q = dict(n=n, g=g, mode=m, target_len=n // max(g) + 1)
+            if m == "store":
+                q["out"] = torch.zeros((oracle.dp_count(n, g), len(g)), dtype=torch.int32,
+                                       device="cuda")
+            qs.append(q)
+    qs += [q for q in tiny_queries(31, 60) if q["mode"] != "store"]
+    try:
+        fz.config_set("skip_empty_rows", mode)
+        res = fz.batch(qs)
+    finally:
+        fz.config_set("skip_empty_rows", 0)
+    for q, r in zip(qs, res):
+        check_against_oracle(q, r)

@@ -90,6 +90,52 @@ def test_small_inputs_all_consumers(fz, n, g):
         assert rows(fz.unrank(n, g, ranks)) == rows(want)
 
 
+# Sparse sets: most rows (a_1..a_{d-3}) have no element, and the walker skips
+# empty subtrees by the count table.  Each is run with skipping automatic,
+# forced on and forced off.
+SPARSE = [
+    (6000, [75, 10, 424, 529, 447, 983, 831, 750]),
+    (9000, [94, 273, 587, 303, 743, 849, 336, 896]),
+    (5000, [5, 357, 149, 958, 122, 560, 756, 746]),
+    (12000, [733, 596, 429, 36, 995, 476, 741]),
+    (3000, [13, 37, 38, 40, 41, 42]),
+    (20000, [268, 422, 83, 155, 171, 995, 592, 886]),
+]
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["auto", "skip", "noskip"])
+@pytest.mark.parametrize("n,g", SPARSE)
+def test_sparse_sets_skip_empty_rows(fz, n, g, mode):
+    want = oracle.store(n, g)
+    try:
+        fz.config_set("skip_empty_rows", mode)
+        assert fz.count(n, g) == len(want)
+        got, total = fz.enumerate_host(n, g, len(want))
+        assert total == len(want) and np.array_equal(got, want)
+        h, lo, hi = fz.length_hist(n, g)
+        assert np.array_equal(h, oracle.dp_hist(n, g))
+        lens = want.astype(np.int64).sum(axis=1)
+        for t in (int(lens.min()), int(lens.max()), int(lens.min()) - 1, int(lens.max()) + 1):
+            assert fz.exists(n, g, t) == bool((lens == t).any())
+    finally:
+        fz.config_set("skip_empty_rows", 0)
+
+
+@pytest.mark.parametrize("n,g", [c for c in tiny_cases(23, 80) + EDGE if len(c[1]) >= 4])
+def test_small_inputs_forced_row_skipping(fz, n, g):
+    want = oracle.store(n, g)
+    try:
+        fz.config_set("skip_empty_rows", 1)
+        assert fz.count(n, g) == len(want)
+        got, total = fz.enumerate_host(n, g, len(want) + 3)
+        assert total == len(want) and rows(got) == rows(want)
+        h, lo, hi = fz.length_hist(n, g)
+        oh, olo, ohi = oracle.hist(n, g)
+        assert np.array_equal(h, oh) and lo == olo and hi == ohi
+    finally:
+        fz.config_set("skip_empty_rows", 0)
+
+
 def test_unrank_rejects_rank_out_of_range(fz):
     with pytest.raises(fz.FzError) as e:
         fz.unrank(100, [3, 5, 7], [oracle.dp_count(100, [3, 5, 7])])
@@ -142,7 +188,8 @@ def test_single_small_unrank(fz, small):
 
 
 @pytest.mark.parametrize("knob,value", [("slices_per_wave", 1), ("slices_per_wave", 37),
-                                        ("workgroups_per_cu", 1), ("workgroups_per_cu", 3)])
+                                        ("workgroups_per_cu", 1), ("workgroups_per_cu", 3),
+                                        ("skip_empty_rows", 1), ("skip_empty_rows", 2)])
 def test_tuning_knobs_do_not_change_results(fz, small, knob, value):
     n, g, want = small
     try:
