@@ -280,6 +280,11 @@ def main():
     out = torch.empty((M, len(g)), dtype=torch.int32, device="cuda")
     log(f"workload: n={n} g={g} |Z|={N} store rows={M}")
 
+    # The workload keeps the generators in drawn order: the count walks in
+    # that order too (the library would otherwise walk order-free consumers
+    # in descending generator order, timed separately below).
+    fz.config_set("walk_order", 1)
+
     def step():
         c = fz.count(n, g)
         st_count = fz.last_stats()
@@ -359,6 +364,24 @@ def main():
         "store_factorizations_per_s": M / avg_store_s,
         "kernel_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in kt.items()},
         "walker_stats": st,
+    }
+    # the same count in the library's default (descending) walk order
+    fz.config_set("walk_order", 0)
+    fz.count(n, g)
+    fz.profile_reset()
+    fz.profile_enable(True)
+    for _ in range(max(args.steps, 1)):
+        if fz.count(n, g) != N:
+            raise RuntimeError("wrong count in descending walk order")
+    fz.profile_enable(False)
+    st_desc = fz.last_stats()
+    desc_ms, desc_n = fz.profile_read("enum.count")
+    res["count_descending_walk_order"] = {
+        "avg_launch_ms": desc_ms / max(desc_n, 1),
+        "factorizations_per_s": N / (desc_ms / 1e3 / max(desc_n, 1)),
+        "ops_per_launch": OPS_PER_ELEMENT * st_desc["elements"] +
+                          OPS_PER_PREFIX * st_desc["prefixes"],
+        "walker_stats": st_desc,
     }
     del out
     torch.cuda.empty_cache()

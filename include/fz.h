@@ -234,9 +234,14 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * resident wavefront), "workgroups_per_cu" (persistent workgroups per compute
  * unit), "work_row", "work_chunk", "work_element" (weights, in 1/64 of a
  * wavefront instruction, of a row a_1..a_{d-3}, of a 64-lane chunk of a row
- * and of an element, when slices are cut to equal work).  FZ_EINVAL for an
- * unknown key or a value outside 0..2^20.  Results never depend on the
- * knobs. */
+ * and of an element, when slices are cut to equal work), "skip_empty_rows"
+ * (0: for sets with few elements per row, skip rows and subtrees that the
+ * count table shows empty; 1: always; 2: never), "walk_order" (0: count,
+ * histogram and predicate walk the set with the generators in descending
+ * order, which visits the fewest rows; 1: in the caller's order; stores
+ * always use the caller's order, their output order).  FZ_EINVAL for an
+ * unknown key or a value outside its range (0..2^20 for the sizes and
+ * weights).  Results never depend on the knobs. */
 int fz_config_set(const char *key, int64_t value);
 
 /* Autotuner.  Runs the given queries (one fz_batch call when nq > 1, else the

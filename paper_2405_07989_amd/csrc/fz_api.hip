@@ -61,6 +61,7 @@ uint32_t g_work_row = 0;
 uint32_t g_work_chunk = 0;
 uint32_t g_work_elem = 0;
 uint32_t g_prune_mode = 0; // 0: by the set's density, 1: always, 2: never
+uint32_t g_walk_order = 0; // 0: descending for order-free consumers, 1: the caller's
 
 bool worth_pruning(const FzPlan &P);
 
@@ -247,6 +248,27 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
     return FZ_OK;
 }
 
+// Plan of a walk whose result does not depend on the coordinate order
+// (count, histogram of lengths, predicate on the length): the same set is
+// walked with its generators in descending order, which leaves the fewest
+// rows (prefixes of the largest generators) and lane prefixes, and the
+// longest progressions (the two smallest generators last).  Validation and
+// its errors are those of the caller's order.  Stores keep the caller's
+// order: it is their output order.
+int make_walk_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *P)
+{
+    int rc = make_plan(n, g, d, mode, P);
+    if (rc || mode == FZM_STORE || g_walk_order == 1 || d < 2) return rc;
+    uint32_t s[FZ_MAX_D];
+    std::memcpy(s, g, d * sizeof(uint32_t));
+    std::stable_sort(s, s + d, [](uint32_t x, uint32_t y) { return x > y; });
+    if (std::equal(s, s + d, g)) return FZ_OK;
+    FzPlan Q;
+    if (make_plan(n, s, d, mode, &Q)) return FZ_OK; // keep the caller's order
+    *P = Q;
+    return FZ_OK;
+}
+
 void prof_begin(hipStream_t s, hipEvent_t *ev)
 {
     *ev = nullptr;
@@ -355,7 +377,7 @@ int do_count(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count, void *s
 {
     if (count == nullptr) return FZ_EINVAL;
     FzPlan P;
-    int rc = make_plan(n, g, d, FZM_COUNT, &P);
+    int rc = make_walk_plan(n, g, d, FZM_COUNT, &P);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     Ctx *c;
@@ -527,7 +549,7 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
         const fz_query &q = qs[i];
         if (q.mode > FZ_MODE_STORE) { S.qst[i] = FZ_EINVAL; continue; }
         FzPlan &P = Q[i].plan;
-        int e = make_plan(q.n, q.g, q.d, q.mode, &P);
+        int e = make_walk_plan(q.n, q.g, q.d, q.mode, &P);
         if (!e && q.mode == FZ_MODE_HIST && (q.bins == nullptr || q.nbins < P.nbins)) e = FZ_EINVAL;
         if (!e && q.mode == FZ_MODE_STORE && q.d_out == nullptr && q.max_tuples > 0) e = FZ_EINVAL;
         if (e) {
@@ -829,7 +851,7 @@ int fz_length_hist(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *bins, ui
 {
     if (bins == nullptr || min_len == nullptr || max_len == nullptr) return FZ_EINVAL;
     FzPlan P;
-    int rc = make_plan(n, g, d, FZM_HIST, &P);
+    int rc = make_walk_plan(n, g, d, FZM_HIST, &P);
     if (rc) return rc;
     if (nbins < P.nbins) return FZ_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -857,7 +879,7 @@ int fz_exists(uint64_t n, const uint32_t *g, uint32_t d, uint64_t target_len, in
 {
     if (found == nullptr) return FZ_EINVAL;
     FzPlan P;
-    int rc = make_plan(n, g, d, FZM_EXISTS, &P);
+    int rc = make_walk_plan(n, g, d, FZM_EXISTS, &P);
     if (rc) return rc;
     P.target_len = target_len;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -975,6 +997,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "work_chunk") == 0) g_work_chunk = (uint32_t)value;
     else if (std::strcmp(key, "work_element") == 0) g_work_elem = (uint32_t)value;
     else if (std::strcmp(key, "skip_empty_rows") == 0 && value <= 2) g_prune_mode = (uint32_t)value;
+    else if (std::strcmp(key, "walk_order") == 0 && value <= 1) g_walk_order = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

@@ -153,8 +153,9 @@ def test_autotune_keeps_results(fz):
             assert np.array_equal(a["bins"], b["bins"])
 
 
-@pytest.mark.parametrize("mode", [1, 2], ids=["skip", "noskip"])
-def test_row_skipping_in_a_batch(fz, mode):
+@pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
+@pytest.mark.parametrize("mode", [0, 1, 2], ids=["auto", "skip", "noskip"])
+def test_row_skipping_in_a_batch(fz, mode, order):
     from test_gpu_parity import SPARSE
     qs = []
     for n, g in SPARSE:
@@ -167,8 +168,10 @@ def test_row_skipping_in_a_batch(fz, mode):
     qs += [q for q in tiny_queries(31, 60) if q["mode"] != "store"]
     try:
         fz.config_set("skip_empty_rows", mode)
+        fz.config_set("walk_order", order)
         res = fz.batch(qs)
     finally:
         fz.config_set("skip_empty_rows", 0)
+        fz.config_set("walk_order", 0)
     for q, r in zip(qs, res):
         check_against_oracle(q, r)

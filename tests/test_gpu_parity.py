@@ -103,12 +103,14 @@ SPARSE = [
 ]
 
 
+@pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
 @pytest.mark.parametrize("mode", [0, 1, 2], ids=["auto", "skip", "noskip"])
 @pytest.mark.parametrize("n,g", SPARSE)
-def test_sparse_sets_skip_empty_rows(fz, n, g, mode):
+def test_sparse_sets_skip_empty_rows(fz, n, g, mode, order):
     want = oracle.store(n, g)
     try:
         fz.config_set("skip_empty_rows", mode)
+        fz.config_set("walk_order", order)
         assert fz.count(n, g) == len(want)
         got, total = fz.enumerate_host(n, g, len(want))
         assert total == len(want) and np.array_equal(got, want)
@@ -119,6 +121,7 @@ def test_sparse_sets_skip_empty_rows(fz, n, g, mode):
             assert fz.exists(n, g, t) == bool((lens == t).any())
     finally:
         fz.config_set("skip_empty_rows", 0)
+        fz.config_set("walk_order", 0)
 
 
 @pytest.mark.parametrize("n,g", [c for c in tiny_cases(23, 80) + EDGE if len(c[1]) >= 4])
@@ -189,7 +192,8 @@ def test_single_small_unrank(fz, small):
 
 @pytest.mark.parametrize("knob,value", [("slices_per_wave", 1), ("slices_per_wave", 37),
                                         ("workgroups_per_cu", 1), ("workgroups_per_cu", 3),
-                                        ("skip_empty_rows", 1), ("skip_empty_rows", 2)])
+                                        ("skip_empty_rows", 1), ("skip_empty_rows", 2),
+                                        ("walk_order", 1)])
 def test_tuning_knobs_do_not_change_results(fz, small, knob, value):
     n, g, want = small
     try:
