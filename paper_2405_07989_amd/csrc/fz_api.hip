@@ -39,7 +39,7 @@ constexpr double kWorkElem[4] = {4, 8, 5, 40}; // count, hist, exists, store
 // A skipped row costs about 1/2 instruction: 64 siblings per ballot scan.
 constexpr uint32_t kWorkSkip = 32;
 // Rows are skipped when the set has fewer elements than this per row.
-constexpr double kPruneElementsPerRow = 64.0;
+constexpr double kPruneElementsPerRow = 0.5;
 
 struct Ctx {
     bool ready = false;
