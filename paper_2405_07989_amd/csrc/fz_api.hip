@@ -518,6 +518,9 @@ void BatchSlot::release()
     h_cap = 0;
     h_bins_cap = 0;
     h_totals_cap = 0;
+    if (tables_ev) (void)hipEventDestroy(tables_ev);
+    tables_ev = nullptr;
+    walk_pending = false;
 }
 
 // Work weights of the batch walker, in its own units (1/8 of the time of an
@@ -531,8 +534,8 @@ constexpr uint32_t kBatchElem[4] = {35, 40, 40, 48}; // count, hist, exists, sto
 // Skipping pays off only on sets with enough rows.
 constexpr double kPruneMinRows = 4096.0;
 
-int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
-                 uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile)
+int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
+                        uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile)
 {
     // plans; a rejected query keeps d = 0 and takes no device work
     std::vector<FzBatchQuery> &Q = S.Q;
@@ -540,7 +543,9 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
     S.qst.assign(nq, FZ_OK);
     S.nq = nq;
     S.n_items = 0;
-    std::vector<double> work(nq, 0.0);
+    S.walk_pending = false;
+    std::vector<double> &work = S.work;
+    work.assign(nq, 0.0);
     double est_total = 0;
     uint32_t maxm = 0, max_du = 0, bstride = 1;
     bool any_hist = false;
@@ -583,7 +588,8 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
     // stores (rows placed by rank), sparse queries (they skip empty rows by
     // the count table) and any query estimated above half a slice -- and the
     // exact modelled work of each, read back to size its slice count.
-    std::vector<uint32_t> tabled;
+    std::vector<uint32_t> &tabled = S.tabled;
+    tabled.clear();
     uint64_t tab_words = 0, res_words = 0, bin_words = 0;
     const double est_target = std::max(est_total / slots, 1.0);
     for (uint32_t i = 0; i < nq; ++i) {
@@ -662,7 +668,7 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
     B.n_bins = bin_words;
     bool any_valid = false;
     for (uint32_t i = 0; i < nq; ++i) any_valid = any_valid || Q[i].plan.d != 0;
-    if (!any_valid) return FZ_OK; // every query was rejected on the host
+    if (!any_valid) return FZ_OK; // every query was rejected on the host: nothing to walk
     FZ_TRY(hipMemcpyAsync(meta, S.h_meta, meta1, hipMemcpyHostToDevice, st));
     const uint32_t *ids = (const uint32_t *)(meta + o_ids);
     if (profile) FZ_LAUNCH("batch.tables", st, fzk_launch_batch_tables(B, n_tab, ids, st));
@@ -670,8 +676,39 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
     if (n_tab)
         FZ_TRY(hipMemcpyAsync(S.h_totals, S.totals.p, (size_t)n_tab * 8, hipMemcpyDeviceToHost,
                               st));
-    // phase 2 restages the query array (host and device copies may move)
-    FZ_TRY(hipStreamSynchronize(st));
+    if (!S.tables_ev) FZ_TRY(hipEventCreateWithFlags(&S.tables_ev, hipEventDisableTiming));
+    FZ_TRY(hipEventRecord(S.tables_ev, st));
+    S.B = B;
+    S.stream = st;
+    S.slots = slots;
+    S.cus = (uint32_t)cus;
+    S.wgcu = wgcu;
+    S.maxm = maxm;
+    S.max_du = max_du;
+    S.lds_bins = lds_bins;
+    S.bstride = bstride;
+    S.profile = profile;
+    S.walk_pending = true;
+    return FZ_OK;
+}
+
+int batch_launch_walk(BatchSlot &S)
+{
+    if (!S.walk_pending) return FZ_OK;
+    S.walk_pending = false;
+    std::vector<FzBatchQuery> &Q = S.Q;
+    const std::vector<double> &work0 = S.work;
+    std::vector<double> work(work0);
+    const std::vector<uint32_t> &tabled = S.tabled;
+    const uint32_t nq = S.nq, n_tab = (uint32_t)tabled.size();
+    const double slots = S.slots;
+    const hipStream_t st = S.stream;
+    const uint32_t bstride = S.bstride, maxm = S.maxm, max_du = S.max_du, lds_bins = S.lds_bins;
+    const uint32_t cus = S.cus, wgcu = S.wgcu;
+    const bool profile = S.profile;
+    FzBatchBufs B = S.B;
+    auto up = [](size_t o) { return (o + 63) & ~(size_t)63; };
+    const size_t o_q = 0;
 
     // Phase 2: cut.  A query with tables gets ceil(work / target) slices of
     // its exact modelled work; the others are one slice each.  Items of large
@@ -725,7 +762,7 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
     FZ_TRY(ensure(S.bounds, (size_t)n_bounds * bstride * 4));
     FZ_TRY(ensure(S.base, (size_t)n_bounds * 8));
     FZ_TRY(ensure(S.recs, (size_t)std::max(n_items, 1u) * sizeof(FzSliceRec)));
-    meta = (uint8_t *)S.meta.p; // a larger staging area moves the device copy
+    uint8_t *meta = (uint8_t *)S.meta.p; // a larger staging area moves the device copy
     FZ_TRY(hipMemcpyAsync(meta, hm, meta2, hipMemcpyHostToDevice, st));
     B.queries = (const FzBatchQuery *)(meta + o_q);
     B.bjobs = (const FzBatchJob *)(meta + o_jobs);
@@ -746,6 +783,15 @@ int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_qu
         FZ_TRY(fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
     }
     return FZ_OK;
+}
+
+int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
+                 uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile)
+{
+    int rc = batch_launch_tables(S, cus, spw, wgcu, qs, nq, st, store_cap, profile);
+    if (rc || !S.walk_pending) return rc;
+    FZ_TRY(hipEventSynchronize(S.tables_ev));
+    return batch_launch_walk(S);
 }
 
 void batch_result(const BatchSlot &S, const fz_query &q, uint32_t i, fz_result *out)

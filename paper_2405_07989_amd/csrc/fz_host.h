@@ -46,14 +46,31 @@ struct BatchSlot {
     std::vector<FzBatchQuery> Q;
     std::vector<int> qst;        // host validation status of each query
     uint32_t nq = 0, n_items = 0;
+    // state kept between the two launch phases
+    std::vector<double> work;
+    std::vector<uint32_t> tabled;
+    FzBatchBufs B{};
+    hipStream_t stream = nullptr;
+    hipEvent_t tables_ev = nullptr; // recorded after the tables and their totals
+    double slots = 0;
+    uint32_t cus = 0, wgcu = 0, maxm = 0, max_du = 0, lds_bins = 0, bstride = 1;
+    bool profile = false;
+    bool walk_pending = false;      // phase 1 queued, phase 2 not yet
     void release();
 };
 
-// Plans qs[0..nq) and queues the whole batch on stream st (count and work
-// tables, residue tables, slice bounds, the persistent walker); returns
-// without waiting.  Store queries with |Z| > store_cap are refused on the
-// device (FZ_E2BIG).  Requires g_mu held when profile is true.  The slot's
-// previous launch must have completed.
+// A batch is launched in two phases.  batch_launch_tables plans qs[0..nq)
+// and queues the count and work tables, residue tables and the readback of
+// each tabled query's modelled work on stream st, then records
+// S.tables_ev (S.walk_pending).  Once that event has completed,
+// batch_launch_walk cuts every query into slices by its work and queues the
+// slice bounds and the persistent walker.  batch_launch does both, waiting
+// in between.  Store queries with |Z| > store_cap are refused on the device
+// (FZ_E2BIG).  Requires g_mu held when profile is true.  The slot's previous
+// launch must have completed.
+int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
+                        uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile);
+int batch_launch_walk(BatchSlot &S);
 int batch_launch(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, const fz_query *qs,
                  uint32_t nq, hipStream_t st, uint64_t store_cap, bool profile);
 

@@ -7,6 +7,9 @@
 // has arrived (up to max_batch queries and the slot's memory budget) and
 // queues it as one batch; so a query that arrives while others run starts in
 // the next free slot, and batches in different slots overlap on the device.
+// A batch is queued in two phases -- count and work tables, then, once
+// their totals are back, the cut and the walk -- and the server thread
+// starts the second from its poll loop, so it never waits on the device.
 // Inside a launch, the wave that finishes a query's last slice writes the
 // query's result to pinned host memory and raises its flag; the server
 // thread polls the flags and hands each result to fz_wait as soon as it is
@@ -124,6 +127,42 @@ void fz_server::run()
         bool any_busy = false, delivered_any = false;
         for (Slot &sl : slots) {
             if (!sl.busy) continue;
+            if (sl.b.walk_pending) {
+                // phase 2 (cut and walk) once the tables and their totals
+                // are in
+                const hipError_t te = hipEventQuery(sl.b.tables_ev);
+                if (te == hipErrorNotReady) {
+                    any_busy = true;
+                    continue;
+                }
+                int rc = te == hipSuccess ? FZ_OK : FZ_EDEVICE;
+                if (te != hipSuccess) (void)hipGetLastError();
+                if (rc == FZ_OK) {
+                    lk.unlock();
+                    {
+                        std::lock_guard<std::mutex> g(g_mu);
+                        rc = batch_launch_walk(sl.b);
+                    }
+                    if (rc == FZ_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) {
+                        (void)hipGetLastError();
+                        rc = FZ_EDEVICE;
+                    }
+                    lk.lock();
+                }
+                if (rc != FZ_OK) {
+                    fz_result r{};
+                    r.status = rc;
+                    r.min_len = UINT64_MAX;
+                    for (uint32_t i = 0; i < (uint32_t)sl.reqs.size(); ++i)
+                        if (!sl.delivered[i]) deliver(sl.reqs[i], r);
+                    if (rc == FZ_EDEVICE) sticky = rc;
+                    sl.left = 0;
+                    sl.busy = false;
+                    sl.reqs.clear();
+                    delivered_any = true;
+                    continue;
+                }
+            }
             // the event first: once it has completed, every flag the launch
             // raises is visible to the polls below
             const hipError_t e = hipEventQuery(sl.done_ev);
@@ -229,10 +268,13 @@ void fz_server::run()
                 std::lock_guard<std::mutex> g(g_mu);
                 uint32_t spw, wgcu;
                 current_knobs(&spw, &wgcu);
-                rc = batch_launch(sl.b, cus, spw, wgcu, sl.qs.data(), (uint32_t)sl.qs.size(),
-                                  sl.stream, store_cap, false);
+                rc = batch_launch_tables(sl.b, cus, spw, wgcu, sl.qs.data(),
+                                         (uint32_t)sl.qs.size(), sl.stream, store_cap, false);
             }
-            if (rc == FZ_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) {
+            // the completion event is recorded after phase 2 (poll loop); a
+            // batch whose queries were all rejected has no phase 2
+            if (rc == FZ_OK && !sl.b.walk_pending &&
+                hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) {
                 (void)hipGetLastError();
                 rc = FZ_EDEVICE;
             }
