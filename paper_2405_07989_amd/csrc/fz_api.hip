@@ -25,7 +25,9 @@ constexpr uint32_t kDefaultWgPerCu = 8;
 constexpr uint32_t kMaxSlices = 1u << 22;
 constexpr size_t kLdsHistBudget = 64 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
-constexpr uint32_t kBatchLdsBins = 1024;         // per-wave LDS histogram in batches
+// per-wave LDS histogram in batches, 8 KB per wave: 1024 64-bit bins, or
+// 2048 32-bit bins for a histogram that needs more
+constexpr uint32_t kBatchLdsBins = 2048;
 // Work model of the walker for cutting slices, in 1/64 of a wave instruction
 // (measured on the compiled walker): a row costs about 50 instructions (the
 // odometer step and the row bounds), a 64-lane chunk about 23 plus one trip
@@ -597,7 +599,7 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
         FzPlan &P = B.plan;
         if (!P.d) continue;
         B.sliced = (P.mode == FZM_STORE || P.prune || work[i] > 0.5 * est_target) ? 1 : 0;
-        P.hist_in_lds = P.mode == FZM_HIST && P.nbins <= lds_bins;
+        P.hist_in_lds = 0; // decided with the cut (32-bit LDS bins need a bound)
         P.restab_in_lds = 0;
         if (B.sliced) {
             B.s_off = tab_words;
@@ -732,6 +734,18 @@ int batch_launch_walk(BatchSlot &S)
                           ? (uint32_t)std::min(std::max(std::ceil(work[i] / target), 1.0), 65536.0)
                           : 1;
         B2.plan.n_slices = B2.n_slices;
+        // 32-bit LDS bins: a bin moves by at most the elements of one item,
+        // and the whole query has at most work / w_el elements (exact work
+        // for a query with tables; the others are small and estimated, so
+        // with a wide margin)
+        const double el_bound = (B2.sliced ? work[i] : 128.0 * work[i]) / B2.plan.w_el;
+        // 64-bit bins when half the area holds them (measured faster), else
+        // 32-bit ones under the bound, else global atomics
+        B2.plan.hist_in_lds = 0;
+        if (B2.plan.mode == FZM_HIST && B2.plan.nbins <= lds_bins / 2) B2.plan.hist_in_lds = 1;
+        else if (B2.plan.mode == FZM_HIST && B2.plan.nbins <= lds_bins &&
+                 el_bound < (double)(1u << 30))
+            B2.plan.hist_in_lds = 2;
         B2.bound_off = n_bounds;
         n_bounds += B2.n_slices + 1;
         order.push_back(i);

@@ -50,7 +50,7 @@ struct FzPlan {
     uint32_t w_el;       // ... of one element
     uint32_t restab_in_lds;
     uint32_t nbins;      // histogram bins (n / min g + 1)
-    uint32_t hist_in_lds;
+    uint32_t hist_in_lds; // histogram bins: 0 global, 1 per-wave LDS 64-bit, 2 per-wave LDS 32-bit
     uint32_t prune;      // skip rows whose subtree is empty (sparse sets; needs S)
     uint32_t w_skip;     // slice-cut weight of a skipped (empty) row
     uint32_t n_slices;   // W

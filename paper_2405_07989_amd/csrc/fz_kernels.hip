@@ -357,7 +357,8 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
 struct WalkIO {
     const int2 *ltab;   // residue table staged in LDS (TLDS)
     const int2 *gtab;   // residue table in global memory (!TLDS)
-    uint64_t *wbins;    // this wave's LDS histogram (difference array)
+    uint64_t *wbins;    // this wave's LDS histogram (difference array), 64-bit bins
+    uint32_t *wbins32;  // ... 32-bit bins (batches: every bin of an item stays below 2^31)
     uint64_t *gbins;    // the global histogram (bins not in LDS)
     uint32_t *found;    // predicate flag (early exit)
     uint32_t *out;      // store destination, row-major [.][d_user]
@@ -373,8 +374,10 @@ struct WalkOut {
 // One run of a lane: cnt elements with lengths len0, len0 + step, ...
 // Recorded in the histogram's strided difference array (stride |step|): +1
 // at the run's shortest length and -1 one stride past its longest; with
-// step 0 all cnt elements have length len0.  Bins are 64-bit and wrap
-// modulo 2^64, so negative entries are two's complement.
+// step 0 all cnt elements have length len0.  Bins wrap, so negative entries
+// are two's complement: 64-bit bins, or 32-bit ones in a batch, where a bin
+// moves by at most the elements of one work item (< 2^30, checked on the
+// host) and is flushed, sign-extended, after every item.
 __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint32_t len0,
                                          uint32_t cnt, int32_t step)
 {
@@ -386,7 +389,10 @@ __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint
         hi = (uint64_t)lo + (uint64_t)cnt * mag;
         inc = 1;
     }
-    if (P.hist_in_lds) {
+    if (P.hist_in_lds == 2) {
+        atomicAdd(&io.wbins32[lo], inc);
+        if (hi < P.nbins) atomicAdd(&io.wbins32[hi], 0xFFFFFFFFu);
+    } else if (P.hist_in_lds) {
         atomicAdd((unsigned long long *)&io.wbins[lo], (unsigned long long)inc);
         if (hi < P.nbins) atomicAdd((unsigned long long *)&io.wbins[hi], ~0ull);
     } else {
@@ -733,6 +739,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.ltab = ltab;
     io.gtab = Bf.restab;
     io.wbins = nullptr;
+    io.wbins32 = nullptr;
     io.gbins = Bf.hist;
     io.found = &Bf.ctl->found;
     io.out = Bf.out;
@@ -1082,10 +1089,10 @@ __global__ void __launch_bounds__(FZK_WG)
     extern __shared__ __align__(16) uint32_t lds[];
     const uint32_t lane = __lane_id();
     const uint32_t wave = threadIdx.x / FZK_WAVE;
-    // per-wave LDS: store scratch (scan, t0, ad0, 64 rows), then 64-bit
-    // histogram bins
+    // per-wave LDS: store scratch (scan, t0, ad0, 64 rows), then the
+    // histogram: lds_bins 32-bit bins or half as many 64-bit ones
     const uint32_t store_words = max_du ? 4 * FZK_WAVE + FZK_WAVE * max_du : 0;
-    const uint32_t bin_words = 2 * lds_bins;
+    const uint32_t bin_words = lds_bins;
     uint32_t *mine = lds + wave * ((store_words + bin_words + 3) & ~3u);
     WalkIO io;
     io.ltab = nullptr;
@@ -1093,7 +1100,7 @@ __global__ void __launch_bounds__(FZK_WG)
     io.s_t0 = (uint32_t *)(io.s_incl + FZK_WAVE);
     io.s_ad0 = io.s_t0 + FZK_WAVE;
     io.s_stage = io.s_ad0 + FZK_WAVE;
-    uint64_t *wb = (uint64_t *)(mine + store_words);
+    uint32_t *wb = mine + store_words;
 
     // uniform spine, as in the single-query walker
     for (;;) {
@@ -1130,10 +1137,13 @@ __global__ void __launch_bounds__(FZK_WG)
             io.out = Q.out;
             io.S = B.tables + Q.s_off; // read only when P.prune (set for cut queries)
             io.wbins = nullptr;
-            const bool lds_hist = mode == FZM_HIST && P.hist_in_lds;
+            io.wbins32 = nullptr;
+            const uint32_t lds_hist = mode == FZM_HIST ? uni(P.hist_in_lds) : 0u;
+            const uint32_t lds_words = lds_hist == 1 ? 2 * P.nbins : P.nbins;
             if (lds_hist) {
-                io.wbins = wb;
-                for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) wb[i] = 0;
+                io.wbins = (uint64_t *)wb;
+                io.wbins32 = wb;
+                for (uint32_t i = lane; i < lds_words; i += FZK_WAVE) wb[i] = 0;
             }
             const bool prune = uni(P.prune) != 0;
             if (mode == FZM_COUNT)
@@ -1148,10 +1158,18 @@ __global__ void __launch_bounds__(FZK_WG)
             else
                 o = prune ? walk_slice<MAXM, FZM_STORE, false, true>(P, M, b0, b1, base, io, lane)
                           : walk_slice<MAXM, FZM_STORE, false, false>(P, M, b0, b1, base, io, lane);
-            if (lds_hist) {
+            if (lds_hist == 1) {
+                const uint64_t *wb64 = (const uint64_t *)wb;
                 for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
-                    const uint64_t h = wb[i];
+                    const uint64_t h = wb64[i];
                     if (h) atomicAdd((unsigned long long *)&io.gbins[i], (unsigned long long)h);
+                }
+            } else if (lds_hist == 2) {
+                for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
+                    const uint32_t h = wb[i];
+                    if (h)
+                        atomicAdd((unsigned long long *)&io.gbins[i],
+                                  (unsigned long long)(int64_t)(int32_t)h);
                 }
             }
         }
@@ -1307,7 +1325,7 @@ static void launch_batch_enum(const FzBatchBufs &b, uint32_t nwg, uint32_t lds_b
                               uint32_t max_du, hipStream_t s)
 {
     const uint32_t store_words = max_du ? 4 * FZK_WAVE + FZK_WAVE * max_du : 0;
-    const uint32_t bin_words = 2 * lds_bins;
+    const uint32_t bin_words = lds_bins;
     const size_t lds = (size_t)(FZK_WG / FZK_WAVE) * ((store_words + bin_words + 3) & ~3u) * 4;
     hipLaunchKernelGGL((fz_batch_enum_kernel<MAXM>), dim3(nwg), dim3(FZK_WG), lds, s, b,
                        lds_bins, max_du);
