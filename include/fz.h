@@ -239,7 +239,10 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * count table shows empty; 1: always; 2: never), "walk_order" (0: count,
  * histogram and predicate walk the set with the generators in descending
  * order, which visits the fewest rows; 1: in the caller's order; stores
- * always use the caller's order, their output order).  FZ_EINVAL for an
+ * always use the caller's order, their output order), "batch_graph" (1:
+ * fz_batch and the server queue a batch's slice bounds and walker as one
+ * HIP graph, updated in place from batch to batch; 0: plain launches; with
+ * profiling on, batches use plain launches).  FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */
 int fz_config_set(const char *key, int64_t value);

@@ -64,6 +64,7 @@ uint32_t g_work_chunk = 0;
 uint32_t g_work_elem = 0;
 uint32_t g_prune_mode = 0; // 0: by the set's density, 1: always, 2: never
 uint32_t g_walk_order = 0; // 0: descending for order-free consumers, 1: the caller's
+uint32_t g_batch_graph = 1; // batch phase 2 as a HIP graph (1) or plain launches (0)
 
 bool worth_pruning(const FzPlan &P);
 
@@ -522,6 +523,8 @@ void BatchSlot::release()
     h_totals_cap = 0;
     if (tables_ev) (void)hipEventDestroy(tables_ev);
     tables_ev = nullptr;
+    if (walk_exec) (void)hipGraphExecDestroy(walk_exec);
+    walk_exec = nullptr;
     walk_pending = false;
 }
 
@@ -694,6 +697,46 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
     return FZ_OK;
 }
 
+// Phase 2 as a HIP graph: the slice-bound and walker launches are captured
+// (their topology is the same for every batch of a slot) and the slot's
+// executable graph is updated in place with the new kernel arguments, or
+// instantiated again when the update is refused (another walker variant).
+int launch_walk_graph(BatchSlot &S, const FzBatchBufs &B, uint32_t maxm, uint32_t nwg,
+                      uint32_t lds_bins, uint32_t max_du, hipStream_t st)
+{
+    hipGraph_t g = nullptr;
+    FZ_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const hipError_t e1 = fzk_launch_batch_slices(B, st);
+    const hipError_t e2 = fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st);
+    const hipError_t e3 = hipStreamEndCapture(st, &g);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        (void)hipGetLastError();
+        if (g) (void)hipGraphDestroy(g);
+        return dev_err_at(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3, "batch graph capture",
+                          __LINE__);
+    }
+    if (S.walk_exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(S.walk_exec, g, &bad, &res) != hipSuccess ||
+            res != hipGraphExecUpdateSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(S.walk_exec);
+            S.walk_exec = nullptr;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!S.walk_exec) e = hipGraphInstantiate(&S.walk_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        S.walk_exec = nullptr;
+        return dev_err_at(e, "hipGraphInstantiate", __LINE__);
+    }
+    FZ_TRY(hipGraphLaunch(S.walk_exec, st));
+    return FZ_OK;
+}
+
 int batch_launch_walk(BatchSlot &S)
 {
     if (!S.walk_pending) return FZ_OK;
@@ -792,6 +835,8 @@ int batch_launch_walk(BatchSlot &S)
     if (profile) {
         FZ_LAUNCH("batch.slices", st, fzk_launch_batch_slices(B, st));
         FZ_LAUNCH("batch.walk", st, fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
+    } else if (g_batch_graph) {
+        return launch_walk_graph(S, B, maxm, nwg, lds_bins, max_du, st);
     } else {
         FZ_TRY(fzk_launch_batch_slices(B, st));
         FZ_TRY(fzk_launch_batch_walk(B, maxm, nwg, lds_bins, max_du, st));
@@ -1058,6 +1103,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "work_element") == 0) g_work_elem = (uint32_t)value;
     else if (std::strcmp(key, "skip_empty_rows") == 0 && value <= 2) g_prune_mode = (uint32_t)value;
     else if (std::strcmp(key, "walk_order") == 0 && value <= 1) g_walk_order = (uint32_t)value;
+    else if (std::strcmp(key, "batch_graph") == 0 && value <= 1) g_batch_graph = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

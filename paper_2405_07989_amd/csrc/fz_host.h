@@ -52,6 +52,7 @@ struct BatchSlot {
     FzBatchBufs B{};
     hipStream_t stream = nullptr;
     hipEvent_t tables_ev = nullptr; // recorded after the tables and their totals
+    hipGraphExec_t walk_exec = nullptr; // phase 2 (slice bounds, walker) as a graph
     double slots = 0;
     uint32_t cus = 0, wgcu = 0, maxm = 0, max_du = 0, lds_bins = 0, bstride = 1;
     bool profile = false;

@@ -175,3 +175,29 @@ def test_row_skipping_in_a_batch(fz, mode, order):
         fz.config_set("walk_order", 0)
     for q, r in zip(qs, res):
         check_against_oracle(q, r)
+
+
+def test_batch_graph_replays_match_plain_launches(fz):
+    """Phase 2 of a batch runs as a HIP graph updated in place from batch to
+    batch; several batches of different shapes, each run with the graph and
+    with plain launches, eager single-query work in between."""
+    w = fzinputs.load_golden()["batch"]["queries"]
+    groups = [w[:200], w[1000:1100], tiny_queries(41, 80), w[2000:2600], w[:200]]
+    for r, group in enumerate(groups):
+        qs = [dict(n=q["n"], g=q["g"], mode=q["mode"],
+                   target_len=q.get("target_len", 0)) for q in group if q["mode"] != "store"]
+        try:
+            fz.config_set("batch_graph", 1)
+            got = fz.batch([dict(q) for q in qs])
+            fz.config_set("batch_graph", 0)
+            want = fz.batch([dict(q) for q in qs])
+        finally:
+            fz.config_set("batch_graph", 1)
+        assert fz.count(10000, [11, 13, 17, 23]) == 3009519  # eager work between replays
+        for q, a, b in zip(qs, got, want):
+            assert a["status"] == b["status"] == 0, (r, q)
+            assert a["found"] == b["found"], (r, q)
+            if not (q["mode"] == "exists" and a["found"]):
+                assert a["count"] == b["count"], (r, q)
+            if q["mode"] == "hist":
+                assert np.array_equal(a["bins"], b["bins"]), (r, q)
