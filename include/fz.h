@@ -242,7 +242,11 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * always use the caller's order, their output order), "batch_graph" (1:
  * fz_batch and the server queue a batch's slice bounds and walker as one
  * HIP graph, updated in place from batch to batch; 0: plain launches; with
- * profiling on, batches use plain launches).  FZ_EINVAL for an
+ * profiling on, batches use plain launches), "pair_table" (single queries
+ * with d >= 4: 0: when the last pair represents few remainders, about
+ * n D / (2 A B) < 1/4, rows walk only the remainders it represents, listed
+ * per residue chain from the count table, and skip empty rows too; 1:
+ * always; 2: never; batches never use it).  FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */
 int fz_config_set(const char *key, int64_t value);

@@ -42,6 +42,8 @@ constexpr double kWorkElem[4] = {4, 8, 5, 40}; // count, hist, exists, store
 constexpr uint32_t kWorkSkip = 32;
 // Rows are skipped when the set has fewer elements than this per row.
 constexpr double kPruneElementsPerRow = 0.5;
+// The pair table is used when fewer pair remainders than this are representable.
+constexpr double kPairMaxFraction = 0.25;
 
 struct Ctx {
     bool ready = false;
@@ -49,7 +51,7 @@ struct Ctx {
     int cus = 0;
     hipStream_t stream = nullptr;
     FzCtl *host_ctl = nullptr; // pinned
-    DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out;
+    DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out, pt;
     BatchSlot batch; // fz_batch
     bool last_batch = false; // fz_last_slices reads the batch's items
     fz_stats last{};
@@ -65,8 +67,11 @@ uint32_t g_work_elem = 0;
 uint32_t g_prune_mode = 0; // 0: by the set's density, 1: always, 2: never
 uint32_t g_walk_order = 0; // 0: descending for order-free consumers, 1: the caller's
 uint32_t g_batch_graph = 1; // batch phase 2 as a HIP graph (1) or plain launches (0)
+uint32_t g_pair_mode = 0;   // pair table: 0 by sparsity of the last pair, 1 always, 2 never
 
 bool worth_pruning(const FzPlan &P);
+bool worth_pair(const FzPlan &P);
+uint64_t pair_words(const FzPlan &P);
 
 struct ProfEntry {
     double ms = 0;
@@ -243,6 +248,7 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
     P->w_el = g_work_elem ? g_work_elem : (uint32_t)kWorkElem[mode & 3];
     P->restab_in_lds = (size_t)2 * P->B * sizeof(int2) <= kLdsRestabBudget;
     P->prune = 0;
+    P->pair = 0;
     P->w_skip = kWorkSkip;
     P->nbins = (uint32_t)(n / ming + 1);
     P->stride = (uint32_t)n + 1;
@@ -323,7 +329,9 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     P.hist_in_lds = (P.mode == FZM_HIST) &&
                     ((size_t)(FZK_WG / FZK_WAVE) * P.nbins * 8 <= kLdsHistBudget);
     P.prune = (g_prune_mode == 1 || (g_prune_mode == 0 && worth_pruning(P))) ? 1 : 0;
-    if (P.d < 4) P.prune = 0;
+    P.pair = worth_pair(P) ? 1 : 0;
+    if (P.pair && g_prune_mode != 2) P.prune = 1; // the pair walker skips empty rows too
+    if (P.d < 4) P.prune = P.pair = 0;
     const uint64_t table_words = (uint64_t)(P.d - 1) * P.stride;
     const uint64_t cost_words = (uint64_t)(P.d - 2) * P.stride;
     FZ_TRY(ensure(c.S, table_words * 8));
@@ -333,6 +341,16 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     FZ_TRY(ensure(c.base, (size_t)(P.n_slices + 1) * 8));
     FZ_TRY(ensure(c.recs, (size_t)P.n_slices * sizeof(FzSliceRec)));
     FZ_TRY(ensure(c.ctl, sizeof(FzCtl)));
+    if (P.pair) {
+        FZ_TRY(ensure(c.pt, pair_words(P) * 8));
+        B.PC = (uint64_t *)c.pt.p;
+        B.PE = (uint32_t *)(B.PC + P.stride);
+        B.PO = B.PE + 2 * ((P.stride + 1) / 2);
+    } else {
+        B.PC = nullptr;
+        B.PE = nullptr;
+        B.PO = nullptr;
+    }
     if (P.mode == FZM_HIST) {
         FZ_TRY(ensure(c.hist, (size_t)P.nbins * 8));
         if (P.hist_in_lds) FZ_TRY(ensure(c.hist_rows, (size_t)L.nwg * P.nbins * 8));
@@ -469,6 +487,25 @@ bool worth_pruning(const FzPlan &P)
     return el < kPruneElementsPerRow * rows;
 }
 
+// A sparse last pair: a remainder v <= n is representable by (A, B) with
+// probability about n D / (2 A B) when that is small, so the lanes of a row
+// walking every x mostly find nothing.  Then the walker reads the
+// representable remainders from the pair table instead (needs M >= 1).
+bool worth_pair(const FzPlan &P)
+{
+    if (P.d < 4 || g_pair_mode == 2) return false;
+    if (g_pair_mode == 1) return true;
+    const double frac = (double)P.n * P.D / (2.0 * (double)P.A * (double)P.B);
+    return frac < kPairMaxFraction;
+}
+
+// Words of a query's pair table: counts (n+1), remainders, chain starts.
+uint64_t pair_words(const FzPlan &P)
+{
+    const uint64_t nc = std::min<uint64_t>(P.G2, P.stride);
+    return (uint64_t)P.stride + (P.stride + 1) / 2 + (nc + 2) / 2;
+}
+
 // Rough work of a query in the walker's units.  With pruning, each element
 // is charged a row and a chunk of its own (an upper bound for a sparse set)
 // and every row the cost of being skipped.
@@ -579,6 +616,9 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
         P.w_chunk = g_work_chunk ? g_work_chunk : kBatchChunk;
         P.w_el = g_work_elem ? g_work_elem : kBatchElem[P.mode & 3];
         P.w_skip = kBatchSkip;
+        // No pair table in a batch: the batch walker is one kernel for all
+        // variants, and the pair variant's registers would halve its occupancy.
+        P.pair = 0;
         work[i] = estimate_work(P);
         est_total += work[i];
         maxm = std::max(maxm, P.d - 3);
@@ -1104,6 +1144,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "skip_empty_rows") == 0 && value <= 2) g_prune_mode = (uint32_t)value;
     else if (std::strcmp(key, "walk_order") == 0 && value <= 1) g_walk_order = (uint32_t)value;
     else if (std::strcmp(key, "batch_graph") == 0 && value <= 1) g_batch_graph = (uint32_t)value;
+    else if (std::strcmp(key, "pair_table") == 0 && value <= 2) g_pair_mode = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

@@ -52,6 +52,7 @@ struct FzPlan {
     uint32_t nbins;      // histogram bins (n / min g + 1)
     uint32_t hist_in_lds; // histogram bins: 0 global, 1 per-wave LDS 64-bit, 2 per-wave LDS 32-bit
     uint32_t prune;      // skip rows whose subtree is empty (sparse sets; needs S)
+    uint32_t pair;       // walk only the pair remainders the last pair represents (pair table)
     uint32_t w_skip;     // slice-cut weight of a skipped (empty) row
     uint32_t n_slices;   // W
     uint32_t stride;     // n + 1: row length of the count table
@@ -97,6 +98,9 @@ struct FzBufs {
     uint64_t *hist_rows;  // nwg x nbins partial histograms
     uint64_t *hist;       // nbins final histogram
     uint32_t *out;        // store destination (row-major [.][d_user])
+    uint64_t *PC;         // pair table (P.pair): n+1 chain prefix counts
+    uint32_t *PE;         //   up to n+1 representable remainders
+    uint32_t *PO;         //   min(G2, n+1) + 1 chain starts
 };
 
 // ---------------------------------------------------------------------------

@@ -115,12 +115,16 @@ __device__ __forceinline__ uint32_t unrank_level(const uint64_t *Srow, uint32_t 
 // itself, its 64-lane chunks and its elements.  t = floor(v / G2) + 1 is the
 // whole row.  Non-decreasing in t.
 __device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM, uint32_t v,
-                                             uint32_t t)
+                                             uint32_t t, const uint64_t *PC)
 {
     if (t == 0) return 0;
     if (P.prune && SM[v] == 0) return P.w_skip; // an empty row is skipped, not walked
     const uint64_t el = SM[v] - (t * (uint64_t)P.G2 <= v ? SM[v - t * P.G2] : 0);
-    const uint64_t chunks = (t + FZK_WAVE - 1) / FZK_WAVE;
+    // lanes visit all t values of x, or with the pair table only the ones
+    // with an element
+    const uint64_t lanes =
+        P.pair ? PC[v] - (t * (uint64_t)P.G2 <= v ? PC[v - t * P.G2] : 0) : (uint64_t)t;
+    const uint64_t chunks = (lanes + FZK_WAVE - 1) / FZK_WAVE;
     uint64_t w = P.w_row + chunks * P.w_chunk;
     const uint64_t we = el * P.w_el;
     return (P.w_el && we / P.w_el != el) ? ~0ull : sat_add(w, we);
@@ -192,9 +196,51 @@ __device__ void chain_scan(uint64_t *row, uint32_t len, uint32_t gk, Below below
     __syncthreads();
 }
 
+// Pair table of a query, after its count table (whole workgroup): a pair
+// remainder w is representable when the last pair has a completion,
+// S[d-2][w] > 0.  PC[v] counts the representable w <= v with w = v (mod G2);
+// PO[r] is where chain r's list starts in PE, PO[nc] the total; PE lists
+// each chain's representable remainders in ascending order.
+__device__ void pair_table(const FzPlan &P, const uint64_t *S, uint64_t *PC, uint32_t *PE,
+                           uint32_t *PO, uint64_t *part)
+{
+    const uint64_t *Sp = S + (uint64_t)(P.d - 2) * P.stride;
+    chain_scan<false>(PC, P.stride, P.G2, [&](uint32_t v) { return Sp[v] ? 1ull : 0ull; }, part);
+    const uint32_t T = blockDim.x, tid = threadIdx.x;
+    const uint32_t nc = P.G2 < P.stride ? P.G2 : P.stride;
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base < nc; base += T) {
+        const uint32_t r = base + tid;
+        uint64_t t = 0;
+        if (r < nc) t = PC[r + fdiv(P.n - r, P.div_G2) * P.G2]; // the chain's last entry
+        part[tid] = t;
+        __syncthreads();
+        for (uint32_t o = 1; o < T; o <<= 1) {
+            const uint64_t x = tid >= o ? part[tid - o] : 0;
+            __syncthreads();
+            part[tid] += x;
+            __syncthreads();
+        }
+        if (r < nc) PO[r] = (uint32_t)(carry + part[tid] - t);
+        carry += part[T - 1];
+        __syncthreads();
+    }
+    if (tid == 0) PO[nc] = (uint32_t)carry;
+    __syncthreads();
+    for (uint32_t v = tid; v <= P.n; v += T)
+        if (Sp[v]) {
+            const uint32_t r = v - fdiv(v, P.div_G2) * P.G2;
+            PE[PO[r] + (uint32_t)PC[v] - 1] = v;
+        }
+    __syncthreads();
+}
+
 // All rows of S (k = d-2..0) and of the work table C (k = M..0) for one
-// query; called by a whole workgroup of 1024 threads.
-__device__ void dp_query(const FzPlan &P, uint64_t *S, uint64_t *C, uint64_t *part)
+// query; called by a whole workgroup of 1024 threads.  PAIR: the
+// pair table too, when P.pair.
+template <bool PAIR>
+__device__ void dp_query(const FzPlan &P, uint64_t *S, uint64_t *C, uint64_t *part, uint64_t *PC,
+                         uint32_t *PE, uint32_t *PO)
 {
     for (int k = (int)P.d - 2; k >= 0; --k) {
         uint64_t *row = S + (uint64_t)k * P.stride;
@@ -206,11 +252,13 @@ __device__ void dp_query(const FzPlan &P, uint64_t *S, uint64_t *C, uint64_t *pa
         else
             chain_scan<true>(row, P.stride, P.g[k], [&](uint32_t v) { return nxt[v]; }, part);
     }
+    if constexpr (PAIR)
+        if (P.pair) pair_table(P, S, PC, PE, PO, part);
     const int M = (int)P.d - 3;
     uint64_t *CM = C + (uint64_t)M * P.stride;
     const uint64_t *SM = S + (uint64_t)M * P.stride;
     for (uint32_t v = threadIdx.x; v <= P.n; v += blockDim.x)
-        CM[v] = row_work(P, SM, v, fdiv(v, P.div_G2) + 1);
+        CM[v] = row_work(P, SM, v, fdiv(v, P.div_G2) + 1, PC);
     __syncthreads();
     for (int k = M - 1; k >= 0; --k) {
         uint64_t *row = C + (uint64_t)k * P.stride;
@@ -222,7 +270,7 @@ __device__ void dp_query(const FzPlan &P, uint64_t *S, uint64_t *C, uint64_t *pa
 __global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
 {
     __shared__ uint64_t part[1024];
-    dp_query(P, Bf.S, Bf.C, part);
+    dp_query<true>(P, Bf.S, Bf.C, part, Bf.PC, Bf.PE, Bf.PO);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,7 +318,7 @@ __global__ void fz_restab_kernel(FzPlan P, FzBufs Bf)
 // Boundary j of a query cut into W slices: writes its prefix a[0..M] (or the
 // sentinel) to out and returns the element rank of its first element.
 __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64_t *C, uint32_t W,
-                                uint32_t j, uint32_t *out)
+                                uint32_t j, uint32_t *out, const uint64_t *PC)
 {
     const uint32_t M = P.d - 3;
     const uint64_t N = S[P.n];
@@ -296,7 +344,7 @@ __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64
             v -= t * P.g[k];
         }
         const uint32_t x = unrank_level(SM, v, P.G2, r);
-        Wtot = acc + row_work(P, SM, v, x + 1);
+        Wtot = acc + row_work(P, SM, v, x + 1, PC);
     }
     uint64_t rc = (Wtot / W) * j + ((Wtot % W) * j) / W;
     uint64_t base = 0;
@@ -312,7 +360,7 @@ __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64
     uint32_t lo = 0, hi = v / P.G2;
     while (lo < hi) {
         const uint32_t mid = lo + (hi - lo + 1) / 2;
-        if (row_work(P, SM, v, mid) <= rc) lo = mid;
+        if (row_work(P, SM, v, mid, PC) <= rc) lo = mid;
         else hi = mid - 1;
     }
     out[M] = lo;
@@ -338,7 +386,7 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
         c->written = 0;
     }
     if (j > W) return;
-    Bf.base[j] = slice_bound(P, Bf.S, Bf.C, W, j, Bf.bounds + (uint64_t)j * (P.d - 2));
+    Bf.base[j] = slice_bound(P, Bf.S, Bf.C, W, j, Bf.bounds + (uint64_t)j * (P.d - 2), Bf.PC);
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +412,11 @@ struct WalkIO {
     uint32_t *out;      // store destination, row-major [.][d_user]
     uint64_t *s_incl;   // store scratch of this wave: scan, t0, ad0, rows
     uint32_t *s_t0, *s_ad0, *s_stage;
+    uint32_t *s_x;      // store scratch: each lane's x, when not consecutive
     const uint64_t *S;  // count table, for skipping empty subtrees (P.prune)
+    const uint64_t *PC; // pair table (P.pair): representable remainders up to v, per chain
+    const uint32_t *PE; //   the representable remainders, ascending per chain
+    const uint32_t *PO; //   where each chain's list starts in PE
 };
 
 struct WalkOut {
@@ -480,7 +532,7 @@ __device__ __forceinline__ bool skip_empty(const FzPlan &P, const uint32_t M, co
     }
 }
 
-template <int MAXM, int MODE, bool TLDS, bool PRUNE>
+template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                                               const uint32_t *b0, const uint32_t *b1,
                                               uint64_t rank, const WalkIO &io, uint32_t lane)
@@ -554,20 +606,12 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     __hip_atomic_load(io.found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (uni(f)) break;
             }
-            for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
-                const uint32_t Rc = Rp - (uint32_t)c * P.G2;
-                const uint32_t Qc = fdiv(Rc, P.div_B);
-                const uint32_t Pc = Rc - Qc * P.B;
-                const bool active = (int32_t)lane <= xlast - c;
-                const uint32_t rho2 = Pc + lr2;
-                const int32_t q2 = (int32_t)(Qc - lq1);
-                const uint32_t ti = active ? rho2 : 0u;
-                const int2 ent = TLDS ? io.ltab[ti] : io.gtab[ti];
-                // a lane with no element starts at -1, so that the common
-                // decrement stays above -(n + 2 A) > -2^31 for every lane
-                int32_t ad0 = q2 - ent.y;
-                ad0 = (active && ad0 >= 0) ? ad0 : -1;
-                lane_pref += active ? 1u : 0u;
+            // One chunk of lane prefixes: lane l has x = xl, the first valid
+            // a[d-2] = t0 and a[d-1] = ad0 there (-1: no element).  For the
+            // store, the x of position j's owner is xbase + j, or s_x[j] when
+            // the lanes' x are not consecutive.  Returns true to stop the walk.
+            auto consume = [&](const uint32_t xl, const uint32_t t0, int32_t ad0, const int32_t xbase,
+                               const bool x_in_lds) -> bool {
                 uint32_t cnt = 0;
                 if constexpr (MODE == FZM_COUNT) {
                     // two candidate steps per trip; the trip test is the
@@ -598,15 +642,14 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     }
                     lane_el += cnt;
                     if (cnt) {
-                        const uint32_t len0 =
-                            plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
+                        const uint32_t len0 = plen + xl + t0 + (uint32_t)ad0;
                         hist_run(P, io, len0, cnt, (int32_t)len_step);
                     }
                 } else if constexpr (MODE == FZM_EXISTS) {
                     // each element's length is compared with the target; the
                     // wave looks at the lanes' verdicts once per chunk
                     int32_t ad = ad0;
-                    uint32_t len = plen + (uint32_t)c + lane + (uint32_t)ent.x + (uint32_t)ad0;
+                    uint32_t len = plen + xl + t0 + (uint32_t)ad0;
                     bool hit = false;
                     for (;;) {
                         const bool c0 = ad >= 0;
@@ -622,8 +665,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     if (__ballot(hit)) {
                         __hip_atomic_store(io.found, 1u, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-                        done = true;
-                        break;
+                        return true;
                     }
                 } else { // FZM_STORE
                     uint64_t L = 0;
@@ -631,8 +673,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     const uint64_t incl = wave_incl_scan64(L, lane);
                     const uint64_t T = readlane64(incl, FZK_WAVE - 1);
                     io.s_incl[lane] = incl;
-                    io.s_t0[lane] = (uint32_t)ent.x;
+                    io.s_t0[lane] = t0;
                     io.s_ad0[lane] = (uint32_t)ad0;
+                    if (x_in_lds) io.s_x[lane] = xl;
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -658,7 +701,8 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
 #pragma unroll
                             for (int q = 0; q < MAXM; ++q)
                                 if (q < (int)M && (uint32_t)q >= P.pad) st_row[q - P.pad] = a[q];
-                            if (M >= P.pad) st_row[M - P.pad] = (uint32_t)c + j;
+                            if (M >= P.pad)
+                                st_row[M - P.pad] = x_in_lds ? io.s_x[j] : (uint32_t)xbase + j;
                             if (M + 1 >= P.pad) st_row[M + 1 - P.pad] = io.s_t0[j] + k * P.ord;
                             st_row[M + 2 - P.pad] = io.s_ad0[j] - k * P.delta;
                         }
@@ -677,7 +721,56 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                     if (rank < lim) n_el += (T < lim - rank) ? T : (lim - rank);
                     rank += T;
-                    if (rank >= lim) {
+                    if (rank >= lim) return true;
+                }
+                return false;
+            };
+            if constexpr (PAIR) {
+                // Only the lane prefixes with an element: the pair remainders
+                // v = Rp - x G2 (x in [xs, xlast]) that the last pair
+                // represents, read from the pair table's chain r = Rp mod G2
+                // in descending v (ascending x).  PC[v] counts the chain's
+                // representable remainders up to v; PE lists them per chain.
+                if (xlast >= xs) {
+                    const uint32_t vhi = Rp - (uint32_t)xs * P.G2;
+                    const uint32_t vlo = Rp - (uint32_t)xlast * P.G2;
+                    const uint32_t r = vhi - fdiv(vhi, P.div_G2) * P.G2;
+                    const uint32_t hiE = uni((uint32_t)io.PC[vhi]);
+                    const uint32_t loE = vlo >= P.G2 ? uni((uint32_t)io.PC[vlo - P.G2]) : 0u;
+                    const uint32_t ro = uni(io.PO[r]);
+                    for (uint32_t b = loE; b < hiE; b += FZK_WAVE) {
+                        const bool active = b + lane < hiE;
+                        const uint32_t kx = b - loE + lane; // position in ascending x
+                        const uint32_t v = active ? io.PE[ro + hiE - 1 - kx] : 0u;
+                        const uint32_t xl = fdiv(Rp - v, P.div_G2);
+                        const uint32_t Qv = fdiv(v, P.div_B);
+                        const uint32_t Pv = v - Qv * P.B;
+                        const int2 ent = TLDS ? io.ltab[Pv + P.B] : io.gtab[Pv + P.B];
+                        int32_t ad0 = (int32_t)(Qv - 1) - ent.y;
+                        ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                        lane_pref += active ? 1u : 0u;
+                        if (consume(xl, (uint32_t)ent.x, ad0, 0, true)) {
+                            done = true;
+                            break;
+                        }
+                    }
+                }
+            } else {
+                for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
+                    const uint32_t Rc = Rp - (uint32_t)c * P.G2;
+                    const uint32_t Qc = fdiv(Rc, P.div_B);
+                    const uint32_t Pc = Rc - Qc * P.B;
+                    const bool active = (int32_t)lane <= xlast - c;
+                    const uint32_t rho2 = Pc + lr2;
+                    const int32_t q2 = (int32_t)(Qc - lq1);
+                    const uint32_t ti = active ? rho2 : 0u;
+                    const int2 ent = TLDS ? io.ltab[ti] : io.gtab[ti];
+                    // a lane with no element starts at -1, so that the common
+                    // decrement stays above -(n + 2 A) > -2^31 for every lane
+                    int32_t ad0 = q2 - ent.y;
+                    ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                    lane_pref += active ? 1u : 0u;
+                    if (consume((uint32_t)c + lane, (uint32_t)ent.x, ad0, c, false)) {
                         done = true;
                         break;
                     }
@@ -717,7 +810,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
 // Single query.  Persistent workgroups of four waves; each wave takes slices
 // from an atomic cursor.
 // LDS: [residue table, 2B int2, when it fits][per-wave consumer scratch].
-template <int M, int MODE, bool TLDS, bool PRUNE>
+// VAR: 0 plain, 1 skipping empty subtrees, 2 also walking only the pair
+// remainders the last pair represents.
+template <int M, int MODE, bool TLDS, int VAR>
 __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
 {
     extern __shared__ __align__(16) uint32_t lds[];
@@ -744,6 +839,9 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.found = &Bf.ctl->found;
     io.out = Bf.out;
     io.S = Bf.S;
+    io.PC = Bf.PC;
+    io.PE = Bf.PE;
+    io.PO = Bf.PO;
     uint64_t *grow = nullptr;
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) {
@@ -753,13 +851,14 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
             for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = 0;
         }
     }
-    // store scratch per wave: scan (64 x u64), t0 and ad0 (64 x u32 each),
-    // then the staging block of 64 rows x d_user words
-    const uint32_t store_words = 4 * FZK_WAVE + FZK_WAVE * P.d_user;
+    // store scratch per wave: scan (64 x u64), t0, ad0 and x (64 x u32
+    // each), then the staging block of 64 rows x d_user words
+    const uint32_t store_words = 5 * FZK_WAVE + FZK_WAVE * P.d_user;
     io.s_incl = (uint64_t *)(scratch + wave * store_words);
     io.s_t0 = (uint32_t *)(io.s_incl + FZK_WAVE);
     io.s_ad0 = io.s_t0 + FZK_WAVE;
-    io.s_stage = io.s_ad0 + FZK_WAVE;
+    io.s_x = io.s_ad0 + FZK_WAVE;
+    io.s_stage = io.s_x + FZK_WAVE;
     __syncthreads();
 
     // The spine of this loop must stay free of lane-dependent branches: every
@@ -777,7 +876,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
         const WalkOut o =
-            walk_slice<M, MODE, TLDS, PRUNE>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
+            walk_slice<M, MODE, TLDS, (VAR >= 1), (VAR == 2)>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -922,8 +1021,8 @@ __global__ void __launch_bounds__(1024) fz_batch_dp_kernel(FzBatchBufs B, const 
 {
     __shared__ uint64_t part[1024];
     const FzBatchQuery &Q = B.queries[ids[blockIdx.x]];
-    const FzPlan P = Q.plan;
-    dp_query(P, B.tables + Q.s_off, B.tables + Q.c_off, part);
+    const FzPlan P = Q.plan; // P.pair is 0: batches walk without the pair table
+    dp_query<false>(P, B.tables + Q.s_off, B.tables + Q.c_off, part, nullptr, nullptr, nullptr);
 }
 
 // Total modelled work C[0][n] of each query with tables, for the host to
@@ -975,7 +1074,7 @@ __global__ void fz_batch_slices_kernel(FzBatchBufs B)
         if (N == ~0ull || C[P.n] == ~0ull) B.res[job.q].status = FZS_OVERFLOW;
         else if (P.mode == FZM_STORE && N > Q.max_total) B.res[job.q].status = FZS_TOOBIG;
     }
-    B.base[bi] = slice_bound(P, S, C, Q.n_slices, job.j, out);
+    B.base[bi] = slice_bound(P, S, C, Q.n_slices, job.j, out, nullptr); // no pair table
 }
 
 // integrate_hist for one wavefront (no workgroup barrier): lane l takes
@@ -1091,7 +1190,7 @@ __global__ void __launch_bounds__(FZK_WG)
     const uint32_t wave = threadIdx.x / FZK_WAVE;
     // per-wave LDS: store scratch (scan, t0, ad0, 64 rows), then the
     // histogram: lds_bins 32-bit bins or half as many 64-bit ones
-    const uint32_t store_words = max_du ? 4 * FZK_WAVE + FZK_WAVE * max_du : 0;
+    const uint32_t store_words = max_du ? 5 * FZK_WAVE + FZK_WAVE * max_du : 0;
     const uint32_t bin_words = lds_bins;
     uint32_t *mine = lds + wave * ((store_words + bin_words + 3) & ~3u);
     WalkIO io;
@@ -1099,7 +1198,8 @@ __global__ void __launch_bounds__(FZK_WG)
     io.s_incl = (uint64_t *)mine;
     io.s_t0 = (uint32_t *)(io.s_incl + FZK_WAVE);
     io.s_ad0 = io.s_t0 + FZK_WAVE;
-    io.s_stage = io.s_ad0 + FZK_WAVE;
+    io.s_x = io.s_ad0 + FZK_WAVE;
+    io.s_stage = io.s_x + FZK_WAVE;
     uint32_t *wb = mine + store_words;
 
     // uniform spine, as in the single-query walker
@@ -1136,6 +1236,8 @@ __global__ void __launch_bounds__(FZK_WG)
             io.gbins = B.bins + Q.bins_off;
             io.out = Q.out;
             io.S = B.tables + Q.s_off; // read only when P.prune (set for cut queries)
+            io.PC = nullptr;
+            io.PE = io.PO = nullptr;
             io.wbins = nullptr;
             io.wbins32 = nullptr;
             const uint32_t lds_hist = mode == FZM_HIST ? uni(P.hist_in_lds) : 0u;
@@ -1146,18 +1248,14 @@ __global__ void __launch_bounds__(FZK_WG)
                 for (uint32_t i = lane; i < lds_words; i += FZK_WAVE) wb[i] = 0;
             }
             const bool prune = uni(P.prune) != 0;
-            if (mode == FZM_COUNT)
-                o = prune ? walk_slice<MAXM, FZM_COUNT, false, true>(P, M, b0, b1, base, io, lane)
-                          : walk_slice<MAXM, FZM_COUNT, false, false>(P, M, b0, b1, base, io, lane);
-            else if (mode == FZM_HIST)
-                o = prune ? walk_slice<MAXM, FZM_HIST, false, true>(P, M, b0, b1, base, io, lane)
-                          : walk_slice<MAXM, FZM_HIST, false, false>(P, M, b0, b1, base, io, lane);
-            else if (mode == FZM_EXISTS)
-                o = prune ? walk_slice<MAXM, FZM_EXISTS, false, true>(P, M, b0, b1, base, io, lane)
-                          : walk_slice<MAXM, FZM_EXISTS, false, false>(P, M, b0, b1, base, io, lane);
-            else
-                o = prune ? walk_slice<MAXM, FZM_STORE, false, true>(P, M, b0, b1, base, io, lane)
-                          : walk_slice<MAXM, FZM_STORE, false, false>(P, M, b0, b1, base, io, lane);
+#define FZ_WALK(MD)                                                                                \
+    (prune ? walk_slice<MAXM, MD, false, true, false>(P, M, b0, b1, base, io, lane)              \
+           : walk_slice<MAXM, MD, false, false, false>(P, M, b0, b1, base, io, lane))
+            if (mode == FZM_COUNT) o = FZ_WALK(FZM_COUNT);
+            else if (mode == FZM_HIST) o = FZ_WALK(FZM_HIST);
+            else if (mode == FZM_EXISTS) o = FZ_WALK(FZM_EXISTS);
+            else o = FZ_WALK(FZM_STORE);
+#undef FZ_WALK
             if (lds_hist == 1) {
                 const uint64_t *wb64 = (const uint64_t *)wb;
                 for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
@@ -1240,45 +1338,49 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
     if (p.mode == FZM_HIST && p.hist_in_lds)
         bytes += (size_t)waves * p.nbins * sizeof(uint64_t);
     if (p.mode == FZM_STORE)
-        bytes += (size_t)waves * (4 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
+        bytes += (size_t)waves * (5 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
     return bytes;
 }
 
-template <int M, bool TLDS, bool PRUNE>
+template <int M, bool TLDS, int VAR>
 static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
     const size_t lds = fzk_enum_lds_bytes(p);
     switch (p.mode) {
     case FZM_COUNT:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_COUNT, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
-                           lds, s, p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_COUNT, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
+                           s, p, b);
         break;
     case FZM_HIST:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
-                           lds, s, p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
+                           s, p, b);
         break;
     case FZM_EXISTS:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
-                           lds, s, p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
+                           s, p, b);
         break;
     default:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS, PRUNE>), dim3(nwg), dim3(FZK_WG),
-                           lds, s, p, b);
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
+                           s, p, b);
         break;
     }
 }
 
-// Skipping empty rows needs at least one row coordinate (M >= 1).
+// Skipping empty rows, and the pair table (which implies it), need at least
+// one row coordinate (M >= 1).
 template <int M>
 static hipError_t launch_enum_m(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
-    constexpr bool CAN_PRUNE = M > 0;
-    if (CAN_PRUNE && p.prune) {
-        if (p.restab_in_lds) launch_enum_mt<M, true, CAN_PRUNE>(p, b, nwg, s);
-        else launch_enum_mt<M, false, CAN_PRUNE>(p, b, nwg, s);
+    constexpr int V1 = M > 0 ? 1 : 0, V2 = M > 0 ? 2 : 0;
+    if (M > 0 && p.pair) {
+        if (p.restab_in_lds) launch_enum_mt<M, true, V2>(p, b, nwg, s);
+        else launch_enum_mt<M, false, V2>(p, b, nwg, s);
+    } else if (M > 0 && p.prune) {
+        if (p.restab_in_lds) launch_enum_mt<M, true, V1>(p, b, nwg, s);
+        else launch_enum_mt<M, false, V1>(p, b, nwg, s);
     } else {
-        if (p.restab_in_lds) launch_enum_mt<M, true, false>(p, b, nwg, s);
-        else launch_enum_mt<M, false, false>(p, b, nwg, s);
+        if (p.restab_in_lds) launch_enum_mt<M, true, 0>(p, b, nwg, s);
+        else launch_enum_mt<M, false, 0>(p, b, nwg, s);
     }
     return hipGetLastError();
 }
@@ -1324,7 +1426,7 @@ template <int MAXM>
 static void launch_batch_enum(const FzBatchBufs &b, uint32_t nwg, uint32_t lds_bins,
                               uint32_t max_du, hipStream_t s)
 {
-    const uint32_t store_words = max_du ? 4 * FZK_WAVE + FZK_WAVE * max_du : 0;
+    const uint32_t store_words = max_du ? 5 * FZK_WAVE + FZK_WAVE * max_du : 0;
     const uint32_t bin_words = lds_bins;
     const size_t lds = (size_t)(FZK_WG / FZK_WAVE) * ((store_words + bin_words + 3) & ~3u) * 4;
     hipLaunchKernelGGL((fz_batch_enum_kernel<MAXM>), dim3(nwg), dim3(FZK_WG), lds, s, b,

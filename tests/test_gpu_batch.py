@@ -201,3 +201,29 @@ def test_batch_graph_replays_match_plain_launches(fz):
                 assert a["count"] == b["count"], (r, q)
             if q["mode"] == "hist":
                 assert np.array_equal(a["bins"], b["bins"]), (r, q)
+
+
+@pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
+def test_sparse_pairs_in_a_batch(fz, order):
+    # Sparse last pairs, which single queries walk by the pair table; a batch
+    # walks them without it, whatever the knob says, and must agree with the
+    # oracle either way.
+    from test_gpu_parity import SPARSE
+    qs = []
+    for n, g in SPARSE:
+        for m in ("count", "hist", "exists", "store"):
+            q = dict(n=n, g=g, mode=m, target_len=n // max(g) + 1)
+            if m == "store":
+                q["out"] = torch.zeros((oracle.dp_count(n, g), len(g)), dtype=torch.int32,
+                                       device="cuda")
+            qs.append(q)
+    qs += [q for q in tiny_queries(37, 60) if q["mode"] != "store"]
+    try:
+        fz.config_set("pair_table", 1)
+        fz.config_set("walk_order", order)
+        res = fz.batch(qs)
+    finally:
+        fz.config_set("pair_table", 0)
+        fz.config_set("walk_order", 0)
+    for q, r in zip(qs, res):
+        check_against_oracle(q, r)

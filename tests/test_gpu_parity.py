@@ -139,6 +139,30 @@ def test_small_inputs_forced_row_skipping(fz, n, g):
         fz.config_set("skip_empty_rows", 0)
 
 
+# The pair table: each row's lanes take only the pair remainders that the
+# last pair represents.  Forced on (and off) against the oracle.
+@pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
+@pytest.mark.parametrize("n,g", [c for c in tiny_cases(29, 40) + EDGE if len(c[1]) >= 4] + SPARSE)
+def test_pair_table_all_consumers(fz, n, g, order):
+    want = oracle.store(n, g)
+    for mode in (1, 2):
+        try:
+            fz.config_set("pair_table", mode)
+            fz.config_set("walk_order", order)
+            assert fz.count(n, g) == len(want)
+            got, total = fz.enumerate_host(n, g, len(want) + 3)
+            assert total == len(want) and rows(got) == rows(want)
+            h, lo, hi = fz.length_hist(n, g)
+            assert np.array_equal(h, oracle.dp_hist(n, g))
+            if len(want):
+                lens = want.astype(np.int64).sum(axis=1)
+                for t in (int(lens.min()), int(lens.max()) + 1):
+                    assert fz.exists(n, g, t) == bool((lens == t).any())
+        finally:
+            fz.config_set("pair_table", 0)
+            fz.config_set("walk_order", 0)
+
+
 def test_unrank_rejects_rank_out_of_range(fz):
     with pytest.raises(fz.FzError) as e:
         fz.unrank(100, [3, 5, 7], [oracle.dp_count(100, [3, 5, 7])])
