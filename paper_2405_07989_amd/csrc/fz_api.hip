@@ -327,7 +327,7 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
     P.hist_in_lds = (P.mode == FZM_HIST) &&
-                    ((size_t)(FZK_WG / FZK_WAVE) * P.nbins * 8 <= kLdsHistBudget);
+                    ((size_t)P.nbins * 8 <= kLdsHistBudget); // one set per workgroup
     P.prune = (g_prune_mode == 1 || (g_prune_mode == 0 && worth_pruning(P))) ? 1 : 0;
     P.pair = worth_pair(P) ? 1 : 0;
     if (P.pair && g_prune_mode != 2) P.prune = 1; // the pair walker skips empty rows too

@@ -7,7 +7,8 @@
 //   fz_slices_kernel    slice bounds cut to equal work (Sec. 4 bounds)
 //   fz_enum_kernel      the walker: bounded lexicographic enumeration with a
 //                       count / length-histogram / predicate / store consumer
-//   fz_finalize_kernel  sums, the slice self-check, histogram reduction
+//   fz_hist_reduce_kernel  sum of the walker workgroups' histogram rows
+//   fz_finalize_kernel  sums, the slice self-check, histogram integration
 //   fz_unrank_kernel    element of a given rank (the fz_unrank entry point)
 //   fz_batch_*          the same steps for many queries in one launch each
 //
@@ -405,7 +406,8 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
 struct WalkIO {
     const int2 *ltab;   // residue table staged in LDS (TLDS)
     const int2 *gtab;   // residue table in global memory (!TLDS)
-    uint64_t *wbins;    // this wave's LDS histogram (difference array), 64-bit bins
+    uint64_t *wbins;    // LDS histogram (difference array), 64-bit bins: the workgroup's
+                        // (single query) or this wave's (batch)
     uint32_t *wbins32;  // ... 32-bit bins (batches: every bin of an item stays below 2^31)
     uint64_t *gbins;    // the global histogram (bins not in LDS)
     uint32_t *found;    // predicate flag (early exit)
@@ -842,13 +844,10 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.PC = Bf.PC;
     io.PE = Bf.PE;
     io.PO = Bf.PO;
-    uint64_t *grow = nullptr;
     if constexpr (MODE == FZM_HIST) {
-        if (P.hist_in_lds) {
-            io.wbins = (uint64_t *)(scratch + wave * 2 * P.nbins);
-            for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) io.wbins[i] = 0;
-            grow = Bf.hist_rows + (uint64_t)blockIdx.x * P.nbins;
-            for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = 0;
+        if (P.hist_in_lds) { // one set of bins for the workgroup's waves
+            io.wbins = (uint64_t *)scratch;
+            for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) io.wbins[i] = 0;
         }
     }
     // store scratch per wave: scan (64 x u64), t0, ad0 and x (64 x u32
@@ -888,11 +887,10 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         }
     }
     if constexpr (MODE == FZM_HIST) {
-        if (P.hist_in_lds) {
-            for (uint32_t i = lane; i < P.nbins; i += FZK_WAVE) {
-                const uint64_t h = io.wbins[i];
-                if (h) atomicAdd((unsigned long long *)&grow[i], (unsigned long long)h);
-            }
+        if (P.hist_in_lds) { // every wave has left the loop: the bins are whole
+            __syncthreads();
+            uint64_t *grow = Bf.hist_rows + (uint64_t)blockIdx.x * P.nbins;
+            for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = io.wbins[i];
         }
     }
 }
@@ -909,12 +907,27 @@ __device__ void integrate_hist(const FzPlan &P, uint64_t *h, uint64_t *part)
     chain_scan<false>(h, P.nbins, mag, [&](uint32_t v) { return h[v]; }, part);
 }
 
+// Adds the walker workgroups' histogram rows (nwg rows of nbins) into hist,
+// zeroed beforehand: thread (bin l, group y) sums rows [y R, (y+1) R) of
+// column l, so every row is read once, coalesced, by the whole chip.
+__global__ void fz_hist_reduce_kernel(const uint64_t *rows, uint32_t nwg, uint32_t nbins,
+                                      uint32_t rows_per_group, uint64_t *hist)
+{
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nbins) return;
+    const uint32_t b0 = blockIdx.y * rows_per_group;
+    const uint32_t b1 = b0 + rows_per_group < nwg ? b0 + rows_per_group : nwg;
+    uint64_t h = 0;
+    for (uint32_t b = b0; b < b1; ++b) h += rows[(uint64_t)b * nbins + l];
+    if (h) atomicAdd((unsigned long long *)&hist[l], (unsigned long long)h);
+}
+
 // ---------------------------------------------------------------------------
 // Finalize: element / row / prefix totals, the slice self-check (each slice
 // must have produced exactly the ranks between its bound and the next), the
-// reduction of the per-workgroup histograms, and min / max length.
+// integration of the histogram, and min / max length.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf, uint32_t nwg)
+__global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf)
 {
     __shared__ uint64_t red[4][1024 / FZK_WAVE];
     __shared__ uint64_t part[1024];
@@ -930,14 +943,6 @@ __global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf, 
     }
     uint64_t lo = ~0ull, hi = 0;
     if (P.mode == FZM_HIST) {
-        if (P.hist_in_lds) {
-            for (uint32_t l = tid; l < P.nbins; l += blockDim.x) {
-                uint64_t h = 0;
-                for (uint32_t b = 0; b < nwg; ++b) h += Bf.hist_rows[(uint64_t)b * P.nbins + l];
-                Bf.hist[l] = h;
-            }
-            __syncthreads();
-        }
         integrate_hist(P, Bf.hist, part);
         for (uint32_t l = tid; l < P.nbins; l += blockDim.x)
             if (Bf.hist[l]) {
@@ -1326,7 +1331,7 @@ hipError_t fzk_launch_slices(const FzPlan &p, const FzBufs &b, hipStream_t s)
 {
     const uint32_t blocks = (p.n_slices + 1 + 255) / 256;
     hipLaunchKernelGGL(fz_slices_kernel, dim3(blocks), dim3(256), 0, s, p, b);
-    if (p.mode == FZM_HIST && !p.hist_in_lds)
+    if (p.mode == FZM_HIST)
         hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.hist, (uint64_t)p.nbins);
     return hipGetLastError();
 }
@@ -1335,8 +1340,7 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
 {
     const uint32_t waves = FZK_WG / FZK_WAVE;
     size_t bytes = p.restab_in_lds ? (size_t)2 * ((2 * p.B + 1) & ~1u) * sizeof(uint32_t) : 0;
-    if (p.mode == FZM_HIST && p.hist_in_lds)
-        bytes += (size_t)waves * p.nbins * sizeof(uint64_t);
+    if (p.mode == FZM_HIST && p.hist_in_lds) bytes += (size_t)p.nbins * sizeof(uint64_t);
     if (p.mode == FZM_STORE)
         bytes += (size_t)waves * (5 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
     return bytes;
@@ -1408,7 +1412,13 @@ hipError_t fzk_launch_enum(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipSt
 
 hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
-    hipLaunchKernelGGL(fz_finalize_kernel, dim3(1), dim3(1024), 0, s, p, b, nwg);
+    if (p.mode == FZM_HIST && p.hist_in_lds && nwg > 0) {
+        constexpr uint32_t kRowsPerGroup = 32;
+        const dim3 grid((p.nbins + 255) / 256, (nwg + kRowsPerGroup - 1) / kRowsPerGroup);
+        hipLaunchKernelGGL(fz_hist_reduce_kernel, grid, dim3(256), 0, s, b.hist_rows, nwg,
+                           p.nbins, kRowsPerGroup, b.hist);
+    }
+    hipLaunchKernelGGL(fz_finalize_kernel, dim3(1), dim3(1024), 0, s, p, b);
     return hipGetLastError();
 }
 

@@ -240,6 +240,27 @@ with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ta
             TABLE1.append(([int(x) for x in _gens.split(",")], int(_n)))
 
 
+
+# Histogram bins: one LDS set per workgroup up to 8192 bins, global atomics
+# beyond; both sides of that bound and of 2048 (the bound of per-wave bins),
+# and a dense set whose runs collide in few bins across a workgroup's waves.
+@pytest.mark.parametrize("n,g", [
+    (6143, [3, 100, 101, 103]), (6144, [3, 100, 101, 103]),
+    (24575, [3, 1000, 1001, 1003]), (24576, [3, 1000, 1001, 1003]),
+    (30000, [5, 11, 13, 17]), (12000, [6, 11, 13, 17, 19]),
+])
+def test_histogram_bin_storage(fz, n, g):
+    want = oracle.dp_hist(n, g)
+    for order in (0, 1):
+        try:
+            fz.config_set("walk_order", order)
+            h, lo, hi = fz.length_hist(n, g)
+        finally:
+            fz.config_set("walk_order", 0)
+        assert len(h) == len(want) and np.array_equal(h, want), (n, g, order)
+        nz = np.nonzero(want)[0]
+        assert (lo, hi) == (int(nz[0]), int(nz[-1]))
+
 @pytest.mark.parametrize("g,n", TABLE1, ids=[f"d{len(r[0])}-n{r[1]}" for r in TABLE1])
 def test_table1_counts(fz, g, n):
     assert fz.count(n, g) == oracle.dp_count(n, g)
