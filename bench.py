@@ -168,7 +168,8 @@ def _serve(fz, qs, gaps=None, inflight=4):
             dt = next_t - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
-        pending.put((i, srv.submit(q)))
+        # outputs were allocated (torch.empty, no kernel) and synchronized up front
+        pending.put((i, srv.submit(q, sync=False)))
     pending.put(None)
     th.join()
     elapsed = time.perf_counter() - t0

@@ -146,6 +146,21 @@ def _check(rc: int, what: str) -> int:
     return rc
 
 
+def _after_torch(stream):
+    """The stream to queue library work on so that it runs after the caller's
+    torch work (a fill of an output tensor, say): the given one; else torch's
+    current stream; torch's default stream is the null stream, which the ABI
+    cannot name (NULL selects the library's own, non-blocking stream), so its
+    pending work is waited for instead."""
+    if stream is not None or not torch.cuda.is_available():
+        return stream
+    cur = torch.cuda.current_stream()
+    if cur.cuda_stream:
+        return cur.cuda_stream
+    cur.synchronize()
+    return None
+
+
 def count(n: int, g, stream=None) -> int:
     """|Z(n, g)| (fz_count / fz_count_stream)."""
     arr, gp = _gens(g)
@@ -197,7 +212,8 @@ def enumerate_host(n: int, g, max_tuples: int):
 def enumerate_device(n: int, g, out, max_tuples: int | None = None, stream=None):
     """Write the lex-smallest rows into ``out`` (a contiguous torch.int32 or
     uint32-compatible CUDA tensor of shape [rows, d]) on the current device
-    (fz_enumerate_device).  Returns (total, written)."""
+    (fz_enumerate_device), after the work already queued on torch's current
+    stream (or on ``stream``).  Returns (total, written)."""
     arr, gp = _gens(g)
     d = len(arr)
     if out.dim() != 2 or out.shape[1] != d or not out.is_contiguous() or out.element_size() != 4:
@@ -206,6 +222,7 @@ def enumerate_device(n: int, g, out, max_tuples: int | None = None, stream=None)
     if cap > out.shape[0]:
         raise ValueError("max_tuples exceeds the rows of out")
     total, written = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    stream = _after_torch(stream)
     _check(_lib.fz_enumerate_device(n, gp, d, _vp(out.data_ptr()), cap, ctypes.byref(total),
                                     ctypes.byref(written), _vp(stream) if stream else None),
            "fz_enumerate_device")
@@ -261,10 +278,14 @@ def batch(queries, stream=None):
     n, g, mode ('count' | 'hist' | 'exists' | 'store'), target_len (exists),
     out (store: a contiguous [rows, d] 32-bit CUDA tensor), max_tuples (store,
     default: out's rows).  Returns one dict per query: status, count, total,
-    found, and bins / min_len / max_len (hist) or written (store)."""
+    found, and bins / min_len / max_len (hist) or written (store).  The batch
+    runs after the work already queued on torch's current stream (or on
+    ``stream``)."""
     nq = len(queries)
     qarr, keep = _marshal(queries)
     rarr = (fz_result * max(nq, 1))()
+    if nq:
+        stream = _after_torch(stream)
     _check(_lib.fz_batch(qarr, rarr, nq, _vp(stream) if stream else None), "fz_batch")
     return [_result_dict(q, rarr[i]) for i, q in enumerate(queries)]
 
@@ -304,7 +325,14 @@ class Server:
         self._h = h
         self._live = {}  # ticket -> (query, host buffers it points to)
 
-    def submit(self, q) -> int:
+    def submit(self, q, sync: bool = True) -> int:
+        """Queue one query; returns its ticket.  The server runs on streams of
+        its own, so a store query's output must be ready when it is
+        submitted: with sync (the default) this waits for torch's current
+        stream first; pass sync=False when the outputs are known to be ready
+        (allocated without a kernel, or synchronized once beforehand)."""
+        if sync and q.get("out") is not None and torch.cuda.is_available():
+            torch.cuda.current_stream().synchronize()
         qarr, keep = _marshal([q])
         t = ctypes.c_uint64(0)
         _check(_lib.fz_submit(self._h, qarr, ctypes.byref(t)), "fz_submit")
