@@ -24,6 +24,7 @@ import pytest
 
 import fzinputs
 import oracle
+from fzcheck import oracle_store
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +76,7 @@ EDGE = [
 
 @pytest.mark.parametrize("n,g", tiny_cases(11, 60) + EDGE)
 def test_small_inputs_all_consumers(fz, n, g):
-    want = oracle.store(n, g)
+    want = oracle_store(n, g)
     assert fz.count(n, g) == len(want)
     got, total = fz.enumerate_host(n, g, len(want) + 3)
     assert total == len(want)
@@ -107,7 +108,7 @@ SPARSE = [
 @pytest.mark.parametrize("mode", [0, 1, 2], ids=["auto", "skip", "noskip"])
 @pytest.mark.parametrize("n,g", SPARSE)
 def test_sparse_sets_skip_empty_rows(fz, n, g, mode, order):
-    want = oracle.store(n, g)
+    want = oracle_store(n, g)
     try:
         fz.config_set("skip_empty_rows", mode)
         fz.config_set("walk_order", order)
@@ -126,7 +127,7 @@ def test_sparse_sets_skip_empty_rows(fz, n, g, mode, order):
 
 @pytest.mark.parametrize("n,g", [c for c in tiny_cases(23, 80) + EDGE if len(c[1]) >= 4])
 def test_small_inputs_forced_row_skipping(fz, n, g):
-    want = oracle.store(n, g)
+    want = oracle_store(n, g)
     try:
         fz.config_set("skip_empty_rows", 1)
         assert fz.count(n, g) == len(want)
@@ -144,7 +145,7 @@ def test_small_inputs_forced_row_skipping(fz, n, g):
 @pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
 @pytest.mark.parametrize("n,g", [c for c in tiny_cases(29, 40) + EDGE if len(c[1]) >= 4] + SPARSE)
 def test_pair_table_all_consumers(fz, n, g, order):
-    want = oracle.store(n, g)
+    want = oracle_store(n, g)
     for mode in (1, 2):
         try:
             fz.config_set("pair_table", mode)
