@@ -534,7 +534,9 @@ __device__ __forceinline__ bool skip_empty(const FzPlan &P, const uint32_t M, co
     }
 }
 
-template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR>
+// FIXED: M == MAXM (a compile-time depth: the single-query walker), which
+// allows the row fast paths below without per-level selects.
+template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                                               const uint32_t *b0, const uint32_t *b1,
                                               uint64_t rank, const WalkIO &io, uint32_t lane)
@@ -545,6 +547,13 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
     const uint64_t lg = (uint64_t)lane * P.G2;
     const uint32_t lq1 = (uint32_t)(lg / P.B) + 1;
     const uint32_t lr2 = P.B - (uint32_t)(lg % P.B);
+    // 64 G2 = c64q B + c64r: the step of a chunk's remainder (c64q wraps
+    // only when no second chunk fits in a row, and is then unused)
+    const uint32_t g2q = fdiv(P.G2, P.div_B);
+    const uint32_t g2r64 = (P.G2 - g2q * P.B) * FZK_WAVE; // < 64 B <= 2^30
+    const uint32_t c64r0q = fdiv(g2r64, P.div_B);
+    const uint32_t c64q = g2q * FZK_WAVE + c64r0q;
+    const uint32_t c64r = g2r64 - c64r0q * P.B;
     const uint32_t len_step = P.ord - P.delta;
     const int32_t delta = (int32_t)P.delta;
     // lengths are < 2^31, so a target beyond 32 bits matches none
@@ -598,9 +607,18 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
             }
             const uint32_t Rp = rr[MAXM];
             const int32_t xhi = (int32_t)fdiv(Rp, P.div_G2);
-            bool last = !end_open;
+            // last row of the slice: the prefix equals the end prefix (the
+            // deepest level differs on almost every row, so it goes first)
+            bool last = false;
+            if (!end_open) {
+                bool deep = true;
+                if constexpr (FIXED && MAXM > 0) deep = a[MAXM - 1] == e[MAXM - 1];
+                if (deep) {
+                    last = true;
 #pragma unroll
-            for (int k = 0; k < MAXM; ++k) last = last && (k >= (int)M || a[k] == e[k]);
+                    for (int k = 0; k < MAXM; ++k) last = last && (k >= (int)M || a[k] == e[k]);
+                }
+            }
             const int32_t xlast = last ? xe - 1 : xhi;
             ++n_rows;
             if constexpr (MODE == FZM_EXISTS) {
@@ -758,10 +776,16 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     }
                 }
             } else {
+                // Rc = Rp - c G2 = Qc B + Pc, stepped by 64 G2 = c64q B + c64r
+                // from chunk to chunk (exact whenever a next chunk exists,
+                // since its remainder is >= 0)
+                uint32_t Qc, Pc;
+                {
+                    const uint32_t Rc = Rp - (uint32_t)xs * P.G2;
+                    Qc = fdiv(Rc, P.div_B);
+                    Pc = Rc - Qc * P.B;
+                }
                 for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
-                    const uint32_t Rc = Rp - (uint32_t)c * P.G2;
-                    const uint32_t Qc = fdiv(Rc, P.div_B);
-                    const uint32_t Pc = Rc - Qc * P.B;
                     const bool active = (int32_t)lane <= xlast - c;
                     const uint32_t rho2 = Pc + lr2;
                     const int32_t q2 = (int32_t)(Qc - lq1);
@@ -776,10 +800,28 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                         done = true;
                         break;
                     }
+                    Pc -= c64r;
+                    Qc -= c64q;
+                    if ((int32_t)Pc < 0) {
+                        Pc += P.B;
+                        Qc -= 1;
+                    }
                 }
             }
             if (done || last) break;
-            // next row: rightmost k < M whose a[k] can grow, deeper coordinates reset
+            // next row.  Usually the deepest level grows by one (with a
+            // compile-time depth, tested first without the general scan).
+            if constexpr (FIXED && MAXM > 0) {
+                if (rr[MAXM] >= P.g[MAXM - 1]) {
+                    a[MAXM - 1] += 1;
+                    rr[MAXM] -= P.g[MAXM - 1];
+                    plen += 1;
+                    xs = 0;
+                    chk = MAXM - 1; // levels above it kept their (non-empty) prefix
+                    continue;
+                }
+            }
+            // else the rightmost k < M whose a[k] can grow, deeper coordinates reset
             int kk = -1;
 #pragma unroll
             for (int k = 0; k < MAXM; ++k)
@@ -875,7 +917,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
         const WalkOut o =
-            walk_slice<M, MODE, TLDS, (VAR >= 1), (VAR == 2)>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
+            walk_slice<M, MODE, TLDS, (VAR >= 1), (VAR == 2), true>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -1254,8 +1296,8 @@ __global__ void __launch_bounds__(FZK_WG)
             }
             const bool prune = uni(P.prune) != 0;
 #define FZ_WALK(MD)                                                                                \
-    (prune ? walk_slice<MAXM, MD, false, true, false>(P, M, b0, b1, base, io, lane)              \
-           : walk_slice<MAXM, MD, false, false, false>(P, M, b0, b1, base, io, lane))
+    (prune ? walk_slice<MAXM, MD, false, true, false, false>(P, M, b0, b1, base, io, lane)              \
+           : walk_slice<MAXM, MD, false, false, false, false>(P, M, b0, b1, base, io, lane))
             if (mode == FZM_COUNT) o = FZ_WALK(FZM_COUNT);
             else if (mode == FZM_HIST) o = FZ_WALK(FZM_HIST);
             else if (mode == FZM_EXISTS) o = FZ_WALK(FZM_EXISTS);
