@@ -28,9 +28,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Published MI355X peaks.  The walker's count mode is integer-ALU work: 256
-# CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 int32 lane-ops/s.
-PEAK_INT32_OPS = 256 * 4 * 16 * 2.4e9
+# Published MI355X peaks.  The walker's count mode is integer-ALU work.  The
+# published fp32 vector rate, 157.3 TFLOP/s = 2 FLOP x 128 lanes per CU per
+# cycle x 256 CUs x 2.4 GHz, gives the vector lane rate: 128 x 256 x 2.4e9 =
+# 7.86e13 int32 lane-ops/s (fz_probe_int_valu measures ~7.5e13 for 32-bit
+# adds on the device).
+PEAK_INT32_OPS = 128 * 256 * 2.4e9
 PEAK_HBM_BYTES = 8.0e12
 # Algorithmic int32 work of the count walker (stated with the derivation in
 # the design notes): per element, advance the last pair, test a_d >= 0 and
@@ -311,6 +314,8 @@ def main():
 
     ms_step = elapsed * 1e3 / args.steps
     value = (N + M) / (elapsed / args.steps)
+    valu_probe = fz.probe_int_valu()  # after the timed steps
+    log(f"int32 add probe: {valu_probe['lane_ops_per_s'] / 1e12:.2f} Tops/s")
     kt = {k: fz.profile_read(k) for k in ["dp", "restab", "slices", "enum.count", "enum.store",
                                           "finalize"]}
     cnt_ms, cnt_n = kt["enum.count"]
@@ -350,6 +355,8 @@ def main():
             "traffic": None,
             "ops_per_launch": ops,
             "avg_launch_ms": avg_count_s * 1e3,
+            # the device's own sustained int32 add rate (fz_probe_int_valu)
+            "measured_int_add_peak": valu_probe["lane_ops_per_s"] / 1e12,
         },
         "store_roofline": {
             "bound": "hbm",

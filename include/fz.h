@@ -284,6 +284,14 @@ int fz_profile_read(const char *kernel, double *total_ms, uint64_t *launches);
  * stays valid until the thread's next failing call. */
 const char *fz_last_error(void);
 
+/* Diagnostic: the current device's sustained int32 vector-ALU rate, in lane
+ * operations per second (*lane_ops_per_s), from a kernel in which every lane
+ * runs eight independent chains of 32-bit adds; *ms (may be NULL) is the
+ * kernel's best time of three.  The ceiling that the count walker's
+ * integer-op rate is compared with.  Takes ~0.1 s; FZ_EINVAL for a NULL
+ * rate, FZ_EDEVICE / FZ_ENOMEM on HIP errors. */
+int fz_probe_int_valu(double *lane_ops_per_s, double *ms);
+
 /* Static description of a status code. */
 const char *fz_strerror(int status);
 

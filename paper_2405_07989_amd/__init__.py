@@ -122,6 +122,8 @@ _SIGS = {
     "fz_wait": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(fz_result)]),
     "fz_server_stats_read": (ctypes.c_int, [_vp, ctypes.POINTER(fz_server_stats), ctypes.c_int]),
     "fz_server_destroy": (ctypes.c_int, [_vp]),
+    "fz_probe_int_valu": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -404,6 +406,13 @@ def profile_read(kernel: str):
     ms, n = ctypes.c_double(0), ctypes.c_uint64(0)
     _check(_lib.fz_profile_read(kernel.encode(), ctypes.byref(ms), ctypes.byref(n)), "fz_profile_read")
     return ms.value, n.value
+
+
+def probe_int_valu() -> dict:
+    """fz_probe_int_valu: the device's sustained int32 vector-ALU rate."""
+    rate, ms = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_lib.fz_probe_int_valu(ctypes.byref(rate), ctypes.byref(ms)), "fz_probe_int_valu")
+    return {"lane_ops_per_s": rate.value, "ms": ms.value}
 
 
 def strerror(status: int) -> str:

@@ -22,7 +22,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libfz.so")
-SOURCES = ["fz_kernels.hip", "fz_api.hip", "fz_server.hip"]
+SOURCES = ["fz_kernels.hip", "fz_api.hip", "fz_server.hip", "fz_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
