@@ -593,6 +593,15 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
 #pragma unroll
         for (int k = 0; k < MAXM; ++k) plen += a[k];
         int chk = 0; // skip_empty: levels < chk known to have elements
+        // FIXED: whether the levels above the deepest equal the end prefix's,
+        // recomputed only where those levels change
+        auto upper_equal = [&]() -> bool {
+            bool u = !end_open;
+#pragma unroll
+            for (int k = 0; k + 1 < MAXM; ++k) u = u && a[k] == e[k];
+            return u;
+        };
+        bool upper_eq = FIXED ? upper_equal() : false;
         bool done = false;
         while (!done) {
             if (PRUNE && M > 0) {
@@ -603,6 +612,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     plen = 0;
 #pragma unroll
                     for (int k = 0; k < MAXM; ++k) plen += a[k];
+                    if constexpr (FIXED) upper_eq = upper_equal();
                 }
             }
             const uint32_t Rp = rr[MAXM];
@@ -610,7 +620,10 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
             // last row of the slice: the prefix equals the end prefix (the
             // deepest level differs on almost every row, so it goes first)
             bool last = false;
-            if (!end_open) {
+            if constexpr (FIXED) {
+                if constexpr (MAXM > 0) last = upper_eq && a[MAXM - 1] == e[MAXM - 1];
+                else last = upper_eq;
+            } else if (!end_open) {
                 bool deep = true;
                 if constexpr (FIXED && MAXM > 0) deep = a[MAXM - 1] == e[MAXM - 1];
                 if (deep) {
@@ -785,6 +798,32 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     Qc = fdiv(Rc, P.div_B);
                     Pc = Rc - Qc * P.B;
                 }
+                if constexpr (FIXED) {
+                    // Per lane, in vector registers (the scalar unit is the
+                    // busier one): the table index rho = Pc + lr2 in [1, 2B),
+                    // the quotient q = Qc - lq1 and x; a chunk step lowers Pc
+                    // by c64r, with a borrow from Qc exactly when
+                    // rho - c64r < lr2.
+                    int32_t rho = (int32_t)(Pc + lr2);
+                    int32_t q = (int32_t)(Qc - lq1);
+                    int32_t xl = xs + (int32_t)lane;
+                    for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
+                        const bool active = xl <= xlast;
+                        const int2 ent = TLDS ? io.ltab[rho] : io.gtab[rho];
+                        int32_t ad0 = q - ent.y;
+                        ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                        lane_pref += active ? 1u : 0u;
+                        if (consume((uint32_t)xl, (uint32_t)ent.x, ad0, c, false)) {
+                            done = true;
+                            break;
+                        }
+                        rho -= (int32_t)c64r;
+                        const bool borrow = rho < (int32_t)lr2;
+                        rho += borrow ? (int32_t)P.B : 0;
+                        q -= (int32_t)c64q + (borrow ? 1 : 0);
+                        xl += FZK_WAVE;
+                    }
+                } else
                 for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
                     const bool active = (int32_t)lane <= xlast - c;
                     const uint32_t rho2 = Pc + lr2;
@@ -842,6 +881,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
             for (int k = 0; k < MAXM; ++k) plen += a[k];
             xs = 0;
             chk = kk; // levels above kk kept their (non-empty) prefix
+            if constexpr (FIXED) upper_eq = upper_equal();
         }
     }
     WalkOut o;
