@@ -798,32 +798,6 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     Qc = fdiv(Rc, P.div_B);
                     Pc = Rc - Qc * P.B;
                 }
-                if constexpr (FIXED) {
-                    // Per lane, in vector registers (the scalar unit is the
-                    // busier one): the table index rho = Pc + lr2 in [1, 2B),
-                    // the quotient q = Qc - lq1 and x; a chunk step lowers Pc
-                    // by c64r, with a borrow from Qc exactly when
-                    // rho - c64r < lr2.
-                    int32_t rho = (int32_t)(Pc + lr2);
-                    int32_t q = (int32_t)(Qc - lq1);
-                    int32_t xl = xs + (int32_t)lane;
-                    for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
-                        const bool active = xl <= xlast;
-                        const int2 ent = TLDS ? io.ltab[rho] : io.gtab[rho];
-                        int32_t ad0 = q - ent.y;
-                        ad0 = (active && ad0 >= 0) ? ad0 : -1;
-                        lane_pref += active ? 1u : 0u;
-                        if (consume((uint32_t)xl, (uint32_t)ent.x, ad0, c, false)) {
-                            done = true;
-                            break;
-                        }
-                        rho -= (int32_t)c64r;
-                        const bool borrow = rho < (int32_t)lr2;
-                        rho += borrow ? (int32_t)P.B : 0;
-                        q -= (int32_t)c64q + (borrow ? 1 : 0);
-                        xl += FZK_WAVE;
-                    }
-                } else
                 for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
                     const bool active = (int32_t)lane <= xlast - c;
                     const uint32_t rho2 = Pc + lr2;
