@@ -51,7 +51,7 @@ struct Ctx {
     int cus = 0;
     hipStream_t stream = nullptr;
     FzCtl *host_ctl = nullptr; // pinned
-    DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out, pt;
+    DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out, pt, dpart;
     BatchSlot batch; // fz_batch
     bool last_batch = false; // fz_last_slices reads the batch's items
     fz_stats last{};
@@ -341,6 +341,7 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     FZ_TRY(ensure(c.base, (size_t)(P.n_slices + 1) * 8));
     FZ_TRY(ensure(c.recs, (size_t)P.n_slices * sizeof(FzSliceRec)));
     FZ_TRY(ensure(c.ctl, sizeof(FzCtl)));
+    FZ_TRY(ensure(c.dpart, (size_t)FZK_DP_UNITS * 8));
     if (P.pair) {
         FZ_TRY(ensure(c.pt, pair_words(P) * 8));
         B.PC = (uint64_t *)c.pt.p;
@@ -363,6 +364,7 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     B.recs = (FzSliceRec *)c.recs.p;
     B.ctl = (FzCtl *)c.ctl.p;
     B.hist_rows = (uint64_t *)c.hist_rows.p;
+    B.dpart = (uint64_t *)c.dpart.p;
     B.hist = (uint64_t *)c.hist.p;
     B.out = nullptr;
     return FZ_OK;

@@ -21,6 +21,7 @@
 #define FZK_NONE_E (1 << 30)    // residue-table mark: no solution in class
 #define FZK_WAVE 64
 #define FZK_WG 256              // threads per workgroup of the walker
+#define FZK_DP_UNITS 65536      // threads per level of a single query's table scans
 
 enum FzMode { FZM_COUNT = 0, FZM_HIST = 1, FZM_EXISTS = 2, FZM_STORE = 3 };
 
@@ -101,6 +102,7 @@ struct FzBufs {
     uint64_t *PC;         // pair table (P.pair): n+1 chain prefix counts
     uint32_t *PE;         //   up to n+1 representable remainders
     uint32_t *PO;         //   min(G2, n+1) + 1 chain starts
+    uint64_t *dpart;      // FZK_DP_UNITS block sums of the table scans
 };
 
 // ---------------------------------------------------------------------------

@@ -1,6 +1,6 @@
 // fz_kernels.hip -- HIP kernels of libfz for gfx950 (CDNA4, wave64).
 //
-//   fz_dp_kernel        count table S[k][v] (completions of a prefix) and the
+//   fz_dp_*_kernel      count table S[k][v] (completions of a prefix) and the
 //                       work table used to cut slices
 //   fz_restab_kernel    first element of the last-pair progression per
 //                       residue class of the remainder modulo g[d-1]
@@ -108,8 +108,9 @@ __device__ __forceinline__ uint32_t unrank_level(const uint64_t *Srow, uint32_t 
 // work table C models what a wave pays: C[M][v] is the work of one row with
 // remainder v (row_work), and C[k][v] = C[k+1][v] + C[k][v - g_k] sums it
 // over the subtrees, so slices can be cut to equal work.
-// One workgroup builds all rows; a row is g_k independent chains, each cut
-// into row blocks (partial sums, a carry scan, then the final pass).
+// A row is g_k independent chains, each cut into blocks (partial sums, the
+// carries, then the final pass): a batch builds a query's rows in one
+// workgroup, a single query over the whole chip (a launch per pass).
 // Saturating adds: S[0][n] = 2^64-1 flags overflow.
 // ---------------------------------------------------------------------------
 // Work of the first t lanes (x = 0..t-1) of a row with remainder v: the row
@@ -268,10 +269,71 @@ __device__ void dp_query(const FzPlan &P, uint64_t *S, uint64_t *C, uint64_t *pa
     }
 }
 
-__global__ void __launch_bounds__(1024) fz_dp_kernel(FzPlan P, FzBufs Bf)
+// A single query's tables use the whole chip: each row is scanned by
+// FZK_DP_UNITS threads, chain c cut into nb blocks of rpb chain steps (unit
+// u = block b of chain c, u = b cols + c).  Pass 1 sums each block into part;
+// pass 2 adds the sums of the chain's earlier blocks and writes the running
+// sums.  BELOW_DIV: the source row is the indicator of g_{d-1} | v (the row
+// below the last count-table row), else src[v].
+template <bool BELOW_DIV>
+__device__ __forceinline__ uint64_t dp_below(const FzPlan &P, const uint64_t *src, uint32_t v)
+{
+    if constexpr (BELOW_DIV) return (v - fdiv(v, P.div_B) * P.B) == 0 ? 1ull : 0ull;
+    else return src[v];
+}
+
+template <bool BELOW_DIV>
+__global__ void fz_dp_sums_kernel(FzPlan P, const uint64_t *src, uint32_t gk, uint32_t cols,
+                                  uint32_t nb, uint32_t rpb, uint64_t *part)
+{
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= cols * nb) return;
+    const uint32_t c = u % cols, b = u / cols;
+    const uint32_t rows = (P.stride - 1) / gk + 1;
+    const uint32_t i1 = min(rows, (b + 1) * rpb);
+    uint64_t s = 0;
+    for (uint32_t i = b * rpb; i < i1; ++i) {
+        const uint64_t v = (uint64_t)i * gk + c;
+        if (v < P.stride) s = sat_add(s, dp_below<BELOW_DIV>(P, src, (uint32_t)v));
+    }
+    part[u] = s;
+}
+
+template <bool BELOW_DIV>
+__global__ void fz_dp_apply_kernel(FzPlan P, const uint64_t *src, uint64_t *row, uint32_t gk,
+                                   uint32_t cols, uint32_t nb, uint32_t rpb, const uint64_t *part)
+{
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= cols * nb) return;
+    const uint32_t c = u % cols, b = u / cols;
+    const uint32_t rows = (P.stride - 1) / gk + 1;
+    const uint32_t i1 = min(rows, (b + 1) * rpb);
+    uint64_t run = 0;
+    for (uint32_t j = 0; j < b; ++j) run = sat_add(run, part[j * cols + c]);
+    for (uint32_t i = b * rpb; i < i1; ++i) {
+        const uint64_t v = (uint64_t)i * gk + c;
+        if (v < P.stride) {
+            run = sat_add(run, dp_below<BELOW_DIV>(P, src, (uint32_t)v));
+            row[v] = run;
+        }
+    }
+}
+
+// The row of the work table that prices single rows: C[M][v] = row_work.
+__global__ void fz_dp_work_kernel(FzPlan P, FzBufs Bf)
+{
+    const uint32_t M = P.d - 3;
+    uint64_t *CM = Bf.C + (uint64_t)M * P.stride;
+    const uint64_t *SM = Bf.S + (uint64_t)M * P.stride;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v <= P.n; v += gridDim.x * blockDim.x)
+        CM[v] = row_work(P, SM, v, fdiv(v, P.div_G2) + 1, Bf.PC);
+}
+
+// The pair table of a single query (one workgroup), after its count table.
+__global__ void __launch_bounds__(1024) fz_pair_kernel(FzPlan P, FzBufs Bf)
 {
     __shared__ uint64_t part[1024];
-    dp_query<true>(P, Bf.S, Bf.C, part, Bf.PC, Bf.PE, Bf.PO);
+    pair_table(P, Bf.S, Bf.PC, Bf.PE, Bf.PO, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -1370,9 +1432,48 @@ __global__ void fz_zero_kernel(uint64_t *p, uint64_t count)
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+// One row of a single query's tables: row[v] = running sum along the chains
+// mod gk of the source row (or of g_{d-1} | v).
+static void launch_dp_row(const FzPlan &p, const FzBufs &b, bool below_div, const uint64_t *src,
+                          uint64_t *row, uint32_t gk, hipStream_t s)
+{
+    const uint32_t rows = (p.stride - 1) / gk + 1;
+    const uint32_t cols = gk < p.stride ? gk : p.stride;
+    uint32_t nb = cols >= FZK_DP_UNITS ? 1u : FZK_DP_UNITS / cols;
+    nb = nb > 64 ? 64 : nb; // the carry of a block sums at most 63 block sums
+    nb = nb > rows ? rows : nb;
+    const uint32_t rpb = (rows + nb - 1) / nb;
+    const uint32_t units = cols * nb; // <= FZK_DP_UNITS when nb > 1
+    const dim3 grid((units + 255) / 256), blk(256);
+    if (below_div) {
+        if (nb > 1)
+            hipLaunchKernelGGL(fz_dp_sums_kernel<true>, grid, blk, 0, s, p, src, gk, cols, nb, rpb, b.dpart);
+        hipLaunchKernelGGL(fz_dp_apply_kernel<true>, grid, blk, 0, s, p, src, row, gk, cols, nb, rpb,
+                           b.dpart);
+    } else {
+        if (nb > 1)
+            hipLaunchKernelGGL(fz_dp_sums_kernel<false>, grid, blk, 0, s, p, src, gk, cols, nb, rpb, b.dpart);
+        hipLaunchKernelGGL(fz_dp_apply_kernel<false>, grid, blk, 0, s, p, src, row, gk, cols, nb, rpb,
+                           b.dpart);
+    }
+}
+
 hipError_t fzk_launch_dp(const FzPlan &p, const FzBufs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(fz_dp_kernel, dim3(1), dim3(1024), 0, s, p, b);
+    for (int k = (int)p.d - 2; k >= 0; --k) {
+        uint64_t *row = b.S + (uint64_t)k * p.stride;
+        const uint64_t *src = b.S + (uint64_t)(k + 1) * p.stride;
+        launch_dp_row(p, b, k + 1 == (int)p.d - 1, src, row, p.g[k], s);
+    }
+    if (p.pair) hipLaunchKernelGGL(fz_pair_kernel, dim3(1), dim3(1024), 0, s, p, b);
+    const uint32_t wblocks = (p.n + 1 + 255) / 256;
+    hipLaunchKernelGGL(fz_dp_work_kernel, dim3(wblocks < 4096 ? wblocks : 4096), dim3(256), 0, s, p, b);
+    const int M = (int)p.d - 3;
+    for (int k = M - 1; k >= 0; --k) {
+        uint64_t *row = b.C + (uint64_t)k * p.stride;
+        const uint64_t *src = b.C + (uint64_t)(k + 1) * p.stride;
+        launch_dp_row(p, b, false, src, row, p.g[k], s);
+    }
     return hipGetLastError();
 }
 
