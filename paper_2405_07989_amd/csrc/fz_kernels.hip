@@ -8,7 +8,8 @@
 //   fz_enum_kernel      the walker: bounded lexicographic enumeration with a
 //                       count / length-histogram / predicate / store consumer
 //   fz_hist_reduce_kernel  sum of the walker workgroups' histogram rows
-//   fz_finalize_kernel  sums, the slice self-check, histogram integration
+//   fz_slice_sums_kernel  totals and the slice self-check
+//   fz_finalize_kernel  histogram integration, min / max length
 //   fz_unrank_kernel    element of a given rank (the fz_unrank entry point)
 //   fz_batch_*          the same steps for many queries in one launch each
 //
@@ -1045,20 +1046,39 @@ __global__ void fz_hist_reduce_kernel(const uint64_t *rows, uint32_t nwg, uint32
 // must have produced exactly the ranks between its bound and the next), the
 // integration of the histogram, and min / max length.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf)
+// Slice totals and the self-check over the whole chip: each wave adds its
+// slices' sums to the control block (zeroed by the slice kernel).
+__global__ void fz_slice_sums_kernel(FzPlan P, FzBufs Bf)
 {
-    __shared__ uint64_t red[4][1024 / FZK_WAVE];
-    __shared__ uint64_t part[1024];
-    const uint32_t tid = threadIdx.x, lane = tid % FZK_WAVE, w = tid / FZK_WAVE;
-    const uint32_t nw = blockDim.x / FZK_WAVE;
     uint64_t el = 0, rows = 0, pref = 0, bad = 0;
-    for (uint32_t s = tid; s < P.n_slices; s += blockDim.x) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n_slices;
+         s += gridDim.x * blockDim.x) {
         const FzSliceRec r = Bf.recs[s];
         el += r.elements;
         rows += r.rows;
         pref += r.prefixes;
         if (P.mode != FZM_EXISTS && r.elements != Bf.base[s + 1] - Bf.base[s]) bad = 1;
     }
+    for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
+        el += __shfl_xor(el, o);
+        rows += __shfl_xor(rows, o);
+        pref += __shfl_xor(pref, o);
+        bad |= __shfl_xor(bad, o);
+    }
+    if (__lane_id() == 0) {
+        FzCtl *c = Bf.ctl;
+        if (el) atomicAdd((unsigned long long *)&c->count, (unsigned long long)el);
+        if (rows) atomicAdd((unsigned long long *)&c->rows, (unsigned long long)rows);
+        if (pref) atomicAdd((unsigned long long *)&c->prefixes, (unsigned long long)pref);
+        if (bad) atomicOr(&c->status, (uint32_t)FZS_MISMATCH);
+    }
+}
+
+__global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf)
+{
+    __shared__ uint64_t part[1024];
+    const uint32_t tid = threadIdx.x, lane = tid % FZK_WAVE, w = tid / FZK_WAVE;
+    const uint32_t nw = blockDim.x / FZK_WAVE;
     uint64_t lo = ~0ull, hi = 0;
     if (P.mode == FZM_HIST) {
         integrate_hist(P, Bf.hist, part);
@@ -1069,37 +1089,23 @@ __global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf)
             }
     }
     for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
-        el += __shfl_xor(el, o);
-        rows += __shfl_xor(rows, o);
-        pref += __shfl_xor(pref, o);
-        bad |= __shfl_xor(bad, o);
         const uint64_t lo2 = __shfl_xor(lo, o), hi2 = __shfl_xor(hi, o);
         lo = lo2 < lo ? lo2 : lo;
         hi = hi2 > hi ? hi2 : hi;
     }
     __shared__ uint64_t mm[2][1024 / FZK_WAVE];
     if (lane == 0) {
-        red[0][w] = el;
-        red[1][w] = rows;
-        red[2][w] = pref;
-        red[3][w] = bad;
         mm[0][w] = lo;
         mm[1][w] = hi;
     }
     __syncthreads();
     if (tid == 0) {
-        uint64_t t[4] = {0, 0, 0, 0};
         uint64_t L = ~0ull, H = 0;
         for (uint32_t i = 0; i < nw; ++i) {
-            for (int q = 0; q < 4; ++q) t[q] = (q == 3) ? (t[q] | red[q][i]) : t[q] + red[q][i];
             L = mm[0][i] < L ? mm[0][i] : L;
             H = mm[1][i] > H ? mm[1][i] : H;
         }
         FzCtl *c = Bf.ctl;
-        c->count = t[0];
-        c->rows = t[1];
-        c->prefixes = t[2];
-        if (t[3]) c->status |= FZS_MISMATCH;
         c->min_len = L;
         c->max_len = H;
         const uint64_t N = c->total;
@@ -1575,6 +1581,8 @@ hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, h
         hipLaunchKernelGGL(fz_hist_reduce_kernel, grid, dim3(256), 0, s, b.hist_rows, nwg,
                            p.nbins, kRowsPerGroup, b.hist);
     }
+    const uint32_t sblocks = (p.n_slices + 255) / 256;
+    hipLaunchKernelGGL(fz_slice_sums_kernel, dim3(sblocks < 256 ? sblocks : 256), dim3(256), 0, s, p, b);
     hipLaunchKernelGGL(fz_finalize_kernel, dim3(1), dim3(1024), 0, s, p, b);
     return hipGetLastError();
 }
