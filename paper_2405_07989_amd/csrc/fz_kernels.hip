@@ -293,9 +293,16 @@ __global__ void fz_dp_sums_kernel(FzPlan P, const uint64_t *src, uint32_t gk, ui
     const uint32_t rows = (P.stride - 1) / gk + 1;
     const uint32_t i1 = min(rows, (b + 1) * rpb);
     uint64_t s = 0;
-    for (uint32_t i = b * rpb; i < i1; ++i) {
-        const uint64_t v = (uint64_t)i * gk + c;
-        if (v < P.stride) s = sat_add(s, dp_below<BELOW_DIV>(P, src, (uint32_t)v));
+    // independent loads first, then the dependent sum
+    for (uint32_t i = b * rpb; i < i1; i += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) {
+            const uint64_t v = (uint64_t)(i + q) * gk + c;
+            x[q] = (i + q < i1 && v < P.stride) ? dp_below<BELOW_DIV>(P, src, (uint32_t)v) : 0;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) s = sat_add(s, x[q]);
     }
     part[u] = s;
 }
@@ -310,12 +317,25 @@ __global__ void fz_dp_apply_kernel(FzPlan P, const uint64_t *src, uint64_t *row,
     const uint32_t rows = (P.stride - 1) / gk + 1;
     const uint32_t i1 = min(rows, (b + 1) * rpb);
     uint64_t run = 0;
-    for (uint32_t j = 0; j < b; ++j) run = sat_add(run, part[j * cols + c]);
-    for (uint32_t i = b * rpb; i < i1; ++i) {
-        const uint64_t v = (uint64_t)i * gk + c;
-        if (v < P.stride) {
-            run = sat_add(run, dp_below<BELOW_DIV>(P, src, (uint32_t)v));
-            row[v] = run;
+    for (uint32_t j = 0; j < b; j += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) x[q] = j + q < b ? part[(j + q) * cols + c] : 0;
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) run = sat_add(run, x[q]);
+    }
+    for (uint32_t i = b * rpb; i < i1; i += 8) {
+        uint64_t x[8];
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) {
+            const uint64_t v = (uint64_t)(i + q) * gk + c;
+            x[q] = (i + q < i1 && v < P.stride) ? dp_below<BELOW_DIV>(P, src, (uint32_t)v) : 0;
+        }
+#pragma unroll
+        for (uint32_t q = 0; q < 8; ++q) {
+            const uint64_t v = (uint64_t)(i + q) * gk + c;
+            run = sat_add(run, x[q]);
+            if (i + q < i1 && v < P.stride) row[v] = run;
         }
     }
 }
