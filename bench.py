@@ -391,6 +391,28 @@ def main():
                           OPS_PER_PREFIX * st_desc["prefixes"],
         "walker_stats": st_desc,
     }
+    # The length-set workload (d = 11, a repeated generator): its length
+    # histogram, timed on its own (not part of the step).
+    import fzinputs
+    ls = fzinputs.load_golden()["length_set"]
+    fz.length_hist(ls["n"], ls["g"])
+    fz.profile_reset()
+    fz.profile_enable(True)
+    for _ in range(max(args.steps, 1)):
+        h, _, _ = fz.length_hist(ls["n"], ls["g"])
+        if int(h.sum()) != ls["count"]:
+            raise RuntimeError("wrong length-set histogram")
+    fz.profile_enable(False)
+    st_ls = fz.last_stats()
+    ls_ms, ls_n = fz.profile_read("enum.hist")
+    res["length_set_hist"] = {
+        "workload": f"d={len(ls['g'])} g={ls['g']} n={ls['n']}: histogram of lengths "
+                    f"({ls['nbins']} bins) of |Z|={ls['count']}",
+        "avg_launch_ms": ls_ms / max(ls_n, 1),
+        "factorizations_per_s": ls["count"] / (ls_ms / 1e3 / max(ls_n, 1)),
+        "walker_stats": st_ls,
+    }
+    log("length-set histogram done")
     del out
     torch.cuda.empty_cache()
     if args.calibrate_copy:
