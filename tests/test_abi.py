@@ -76,6 +76,15 @@ def test_no_device_is_a_clean_error():
     assert e.value.status == fz.FZ_EDEVICE
 
 
+def test_probe_validation():
+    L = fz._lib
+    assert L.fz_probe_int_valu(None, None) == fz.FZ_EINVAL
+    import torch
+    if not torch.cuda.is_available():
+        rate = ctypes.c_double(0)
+        assert L.fz_probe_int_valu(ctypes.byref(rate), None) == fz.FZ_EDEVICE
+
+
 def test_batch_validation_without_a_device():
     L = fz._lib
     assert L.fz_batch(None, None, 0, None) == fz.FZ_OK
