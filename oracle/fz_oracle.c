@@ -22,13 +22,18 @@
  *                      prod_i 1/(1 - y x^{g_i})
  *   fzo_unrank_dp      the r-th element of Z in ascending lex order, by
  *                      counting completions level by level
- *   fzo_first_candidate / fzo_next_candidate
- *                      the paper's descending candidate stream (Sec. 3.2.1,
- *                      Alg. 3.1) with the optional modulo skip (Sec. 3.2.4)
+ *   fzo_dp_series      |Z(v)| for every v = 0..nmax (the same product, all
+ *                      coefficients kept)
+ *   fzo_candidate_stream
+ *                      the paper's descending candidate stream (first
+ *                      candidate of Sec. 3.2.1, successor of Alg. 3.1) with
+ *                      the optional modulo skip (Sec. 3.2.4) and bounds
+ *                      (Sec. 3.1.2, Sec. 4)
  *
  * Readings of the paper taken here (where it is garbled or silent):
- *   - Alg. 3.1 step 2 scans j = 1..d-1: the prose says the final index is
- *     excluded; scanning j = d would try to solve a_{d+1}.
+ *   - Alg. 3.1 looks for the coordinate to lower among positions 1..d-1: the
+ *     prose excludes the final index, and including it would try to solve
+ *     a_{d+1}.
  *   - decrementAndSolve divides by g_{i+1} (the prose once writes g_1).
  *   - Modulo skip: "the order" is the additive order of g_{d-1} modulo g_d,
  *     ord = g_d / gcd(g_{d-1}, g_d).  When a_{d-1} < ord no further valid
@@ -329,43 +334,56 @@ static void first_candidate(fzo_state *s)
     s->end_of_stream = 0;
 }
 
-/* Alg. 3.1 (nextCandidate), in place, with the modulo skip of Sec. 3.2.4 when
- * use_modulo is set.  Returns FZO_EINTERNAL if the residual p of step 6 is not
- * positive (a consequence of Thm. 3.2's hypothesis that must never fail). */
+/* Successor in the descending candidate stream: Alg. 3.1 (nextCandidate),
+ * with the modulo skip of Sec. 3.2.4 when use_modulo is set, written here
+ * from the order it walks rather than as the printed listing.
+ *
+ * In descending lex order, the candidate after a = (a_1..a_d) keeps the
+ * longest prefix it can: let k be the last position before d whose
+ * coordinate is positive (none: the stream is over).  Everything after k
+ * restarts from its largest admissible value, so the successor is
+ *     (a_1, .., a_{k-1}, a_k - step, c, 0, .., 0),
+ * where c is the least value for which the candidate reaches n or more,
+ * c = ceil(p / g_{k+1}) for the residual p = n - sum_{j<=k} a_j g_j; the new
+ * candidate is a factorization exactly when g_{k+1} divides p.  The step is
+ * one, except after a factorization whose last changed position is d-1:
+ * then the next factorization with the same a_1..a_{d-2} has a_{d-1} lower by
+ * the additive order of g_{d-1} modulo g_d (Sec. 3.2.4), and when a_{d-1} is
+ * below that order none is left, so a_{d-1} drops to 0.  The stream also
+ * ends at the first candidate that is <=_lex the bound (Sec. 3.1.2).
+ * Returns FZO_EINTERNAL if the residual is not positive, which Thm. 3.2's
+ * hypothesis rules out. */
 static int next_candidate(fzo_state *s, int use_modulo)
 {
     const uint32_t d = s->d;
     uint64_t *a = s->a;
-    if (s->end_of_stream) return FZO_OK;                      /* step 1 */
-    uint32_t i = 0;                                            /* step 2 */
-    for (uint32_t j = 1; j <= d - 1; j++)
-        if (a[j - 1] > 0) i = j;
-    if (i == 0) {                                              /* step 3 */
+    if (s->end_of_stream) return FZO_OK;
+
+    /* the last positive coordinate among positions 1..d-1 (0-based: k-1) */
+    uint32_t k = d - 1;
+    while (k > 0 && a[k - 1] == 0) k--;
+    if (k == 0) {
         s->end_of_stream = 1;
         return FZO_OK;
     }
-    a[d - 1] = 0;                                              /* step 4 */
-    uint64_t dec = 1;                                          /* step 5 */
-    if (use_modulo && i == d - 1 && s->was_valid) {
-        /* Sec. 3.2.4: after a factorization, the next one with this prefix
-         * has a_{d-1} lowered by the additive order of g_{d-1} mod g_d. */
-        uint64_t ord = s->g[d - 1] / gcd64(s->g[d - 2], s->g[d - 1]);
-        dec = (a[i - 1] >= ord) ? ord : a[i - 1];
+    uint32_t pos = k - 1; /* 0-based index of the coordinate that is lowered */
+
+    uint64_t step = 1;
+    if (use_modulo && pos == d - 2 && s->was_valid) {
+        uint64_t order = s->g[d - 1] / gcd64(s->g[d - 2], s->g[d - 1]);
+        step = a[pos] < order ? a[pos] : order;
     }
-    a[i - 1] -= dec;
-    uint64_t ph = phi(s);                                      /* step 6 */
-    if (ph >= s->n) return FZO_EINTERNAL;
-    uint64_t p = s->n - ph;
-    uint64_t gi1 = s->g[i];                                    /* g_{i+1} */
-    uint64_t m = p / gi1;                                      /* step 7 */
-    uint64_t r = p - m * gi1;                                  /* step 8 */
-    s->was_valid = 1;                                          /* step 9 */
-    if (r != 0) {                                              /* step 10 */
-        m++;
-        s->was_valid = 0;
-    }
-    a[i] = m;                                                  /* step 11 */
-    if (lex_le(a, s->b, d)) s->end_of_stream = 1;              /* step 12 */
+    a[pos] -= step;
+    for (uint32_t j = pos + 1; j < d; j++) a[j] = 0;
+
+    uint64_t used = phi(s);
+    if (used >= s->n) return FZO_EINTERNAL;
+    uint64_t residual = s->n - used;
+    uint64_t gnext = s->g[pos + 1];
+    a[pos + 1] = (residual + gnext - 1) / gnext;      /* ceiling division */
+    s->was_valid = (a[pos + 1] * gnext == residual);
+
+    if (lex_le(a, s->b, d)) s->end_of_stream = 1;
     return FZO_OK;
 }
 

@@ -32,10 +32,17 @@ MUTANTS = {
     "unrank-wrong-level": ("uint64_t c = TT(k + 1, v - t * g[k]);", "uint64_t c = TT(k, v - t * g[k]);"),
     "first-candidate-floor": ("uint64_t x = (s->n + s->g[0] - 1) / s->g[0];",
                               "uint64_t x = s->n / s->g[0];"),
-    "solve-no-round-up": ("        m++;\n        s->was_valid = 0;", "        s->was_valid = 0;"),
-    "modulo-order-transposed": ("uint64_t ord = s->g[d - 1] / gcd64(s->g[d - 2], s->g[d - 1]);",
-                                "uint64_t ord = s->g[d - 2] / gcd64(s->g[d - 2], s->g[d - 1]);"),
-    "solve-wrong-generator": ("uint64_t gi1 = s->g[i];", "uint64_t gi1 = s->g[i - 1];"),
+    "solve-no-round-up": ("a[pos + 1] = (residual + gnext - 1) / gnext;",
+                          "a[pos + 1] = residual / gnext;"),
+    "modulo-order-transposed": ("uint64_t order = s->g[d - 1] / gcd64(s->g[d - 2], s->g[d - 1]);",
+                                "uint64_t order = s->g[d - 2] / gcd64(s->g[d - 2], s->g[d - 1]);"),
+    "solve-wrong-generator": ("uint64_t gnext = s->g[pos + 1];", "uint64_t gnext = s->g[pos];"),
+    "successor-keeps-tail": ("for (uint32_t j = pos + 1; j < d; j++) a[j] = 0;",
+                             "for (uint32_t j = pos + 2; j < d; j++) a[j] = 0;"),
+    "dp-series-skips-last": ("for (uint64_t v = g[i]; v <= nmax; v++)",
+                             "for (uint64_t v = g[i]; v < nmax; v++)"),
+    "dp-series-wrong-shift": ("series[v] = sat_add(series[v], series[v - g[i]]);",
+                              "series[v] = sat_add(series[v], series[v - g[i] + 1]);"),
 }
 
 
@@ -72,6 +79,9 @@ def run_pins():
     for d in (2, 3, 4):
         for n in (5, 12):
             assert oracle.dp_count(n, [1] * d) == math.comb(n + d - 1, d - 1)
+    for g in ([3, 5, 7], [4, 6, 6], [2, 9]):
+        s = oracle.dp_series(40, g)
+        assert [int(x) for x in s] == [len(brute(v, g)) for v in range(41)]
 
 
 def test_pins_pass_on_the_real_oracle():

@@ -259,3 +259,53 @@ def test_single_small_workload_two_routes():
     rng = random.Random(7)
     for r in [0, 1, len(st) - 1] + [rng.randrange(len(st)) for _ in range(20)]:
         assert np.array_equal(oracle.unrank_dp(n, g, r), st[r])
+
+
+@pytest.mark.parametrize("g", [[3, 5, 7], [4, 6, 6, 9], [2, 2, 3], [5], [7, 3],
+                               [11, 13, 17, 23], [1, 1, 1, 1]])
+def test_dp_series_against_walks_and_closed_forms(g):
+    """fzo_dp_series (which chooses the length-set workload's n) pinned by
+    routes that share none of its code: the single-n generating-function
+    count for every v <= 3000, the nested-loop walk for every v <= 300 and
+    every 37th v beyond (repeats included), brute force of the box on small
+    v, and the closed forms C(v+d-1, d-1) (all ones), [g | v] (one
+    generator) and Popoviciu (two coprime generators)."""
+    vmax = 3000
+    s = oracle.dp_series(vmax, g)
+    assert len(s) == vmax + 1 and s.dtype == np.uint64
+    for v in range(vmax + 1):
+        assert int(s[v]) == oracle.dp_count(v, g), (v, g)
+    for v in list(range(301)) + list(range(301, vmax + 1, 37)):
+        if v <= (60 if min(g) == 1 and len(g) > 2 else 1200 if len(g) > 3 else vmax):
+            assert int(s[v]) == oracle.count(v, g), (v, g)
+    for v in range(0, 40):
+        if math.prod(v // x + 1 for x in g) <= 20000:
+            assert int(s[v]) == len(brute(v, g))
+    if all(x == 1 for x in g):
+        assert all(int(s[v]) == math.comb(v + len(g) - 1, len(g) - 1) for v in range(vmax + 1))
+    if len(g) == 1:
+        assert all(int(s[v]) == (v % g[0] == 0) for v in range(vmax + 1))
+    if len(g) == 2 and math.gcd(*g) == 1:
+        assert all(int(s[v]) == popoviciu(v, *g) for v in range(vmax + 1))
+
+
+def test_dp_series_length_set_choice():
+    """The length-set workload's n is the first v whose count reaches 1e11;
+    the series there agrees with the independent single-n DP and with its
+    neighbour, which must still be below 1e11 (the choice is the smallest)."""
+    import json
+    with open(os.path.join(HERE, "golden", "workloads.json")) as f:
+        ls = json.load(f)["length_set"]
+    n, g = ls["n"], ls["g"]
+    s = oracle.dp_series(n, g)
+    assert int(s[n]) == ls["count"] == oracle.dp_count(n, g) >= 10**11
+    assert int(s.max(initial=0) if n == 0 else s[:n].max()) < 10**11
+    assert oracle.dp_count(n - 1, g) == int(s[n - 1])
+
+
+def test_dp_series_overflow_marker():
+    # [x^v] 1/(1-x)^40 = C(v+39, 39) passes 2^64 - 1 near v = 160
+    s = oracle.dp_series(300, [1] * 40)
+    first = next(v for v in range(301) if math.comb(v + 39, 39) >= 2**64 - 1)
+    assert all(int(s[v]) == math.comb(v + 39, 39) for v in range(first))
+    assert all(int(s[v]) == 2**64 - 1 for v in range(first, 301))
