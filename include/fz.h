@@ -21,8 +21,9 @@
  * Conventions shared by every entry point
  *   n, g, d   the element, a HOST pointer to d generators (read during the
  *             call only, never retained), and the dimension.
- *   limits    1 <= d <= FZ_MAX_D; every g_i >= 1; n + 2 max_i g_i < 2^31
- *             (for d = 1 also n + 2 (n + 1) < 2^31); n < 2^30 when d <= 2;
+ *   limits    1 <= d <= FZ_MAX_D; every g_i >= 1; n < 2^31 and
+ *             n + 2 max_i g_i < 2^31 (for d = 1 also n + 2 (n + 1) < 2^31);
+ *             n < 2^30 when d <= 2;
  *             g_d <= FZ_MAX_LAST_GEN.  Breaking one
  *             returns FZ_EINVAL (d, g, NULL pointers) or FZ_EOVERFLOW (sizes)
  *             or FZ_E2BIG (g_d), and no output is written.

@@ -216,6 +216,8 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
     }
     // every coordinate, remainder and walker counter stays a non-negative
     // int32; the virtual generator of d = 1 is n + 1
+    // (each term is bounded before the sum, which then cannot wrap)
+    if (n >= (1ull << 31)) return FZ_EOVERFLOW;
     const uint64_t maxa = d == 1 ? std::max<uint64_t>(maxg, n + 1) : maxg;
     if (n + 2 * maxa >= (1ull << 31)) return FZ_EOVERFLOW;
     if (d <= 2 && n >= (1ull << 30)) return FZ_EOVERFLOW;
@@ -643,7 +645,12 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
         FzBatchQuery &B = Q[i];
         FzPlan &P = B.plan;
         if (!P.d) continue;
-        B.sliced = (P.mode == FZM_STORE || P.prune || work[i] > 0.5 * est_target) ? 1 : 0;
+        // (histograms that may take 32-bit LDS bins get tables too: the
+        // count table bounds their bins exactly)
+        const bool mid_hist = P.mode == FZM_HIST && P.nbins > kBatchLdsBins / 2 &&
+                              P.nbins <= kBatchLdsBins;
+        B.sliced = (P.mode == FZM_STORE || P.prune || mid_hist || work[i] > 0.5 * est_target)
+                       ? 1 : 0;
         P.hist_in_lds = 0; // decided with the cut (32-bit LDS bins need a bound)
         P.restab_in_lds = 0;
         if (B.sliced) {
@@ -685,7 +692,7 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
         FZ_TRY(ensure_pinned((void **)&S.h_bins, &cap, std::max<size_t>(bin_words, 1) * 8));
         S.h_bins_cap = cap / 8;
         cap = S.h_totals_cap * 8;
-        FZ_TRY(ensure_pinned((void **)&S.h_totals, &cap, std::max<size_t>(n_tab, 1) * 8));
+        FZ_TRY(ensure_pinned((void **)&S.h_totals, &cap, std::max<size_t>(n_tab, 1) * 16));
         S.h_totals_cap = cap / 8;
     }
     std::memset(S.h_done, 0, (size_t)nq * 4);
@@ -695,7 +702,7 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
     FZ_TRY(ensure(S.restabs, res_words * sizeof(int2)));
     FZ_TRY(ensure(S.bins, bin_words * 8));
     FZ_TRY(ensure(S.res, (size_t)nq * sizeof(FzBatchResult)));
-    FZ_TRY(ensure(S.totals, (size_t)std::max(n_tab, 1u) * 8));
+    FZ_TRY(ensure(S.totals, (size_t)std::max(n_tab, 1u) * 16));
     FZ_TRY(ensure(S.cursor, 256));
     uint8_t *meta = (uint8_t *)S.meta.p;
 
@@ -721,7 +728,7 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
     if (profile) FZ_LAUNCH("batch.tables", st, fzk_launch_batch_tables(B, n_tab, ids, st));
     else FZ_TRY(fzk_launch_batch_tables(B, n_tab, ids, st));
     if (n_tab)
-        FZ_TRY(hipMemcpyAsync(S.h_totals, S.totals.p, (size_t)n_tab * 8, hipMemcpyDeviceToHost,
+        FZ_TRY(hipMemcpyAsync(S.h_totals, S.totals.p, (size_t)n_tab * 16, hipMemcpyDeviceToHost,
                               st));
     if (!S.tables_ev) FZ_TRY(hipEventCreateWithFlags(&S.tables_ev, hipEventDisableTiming));
     FZ_TRY(hipEventRecord(S.tables_ev, st));
@@ -801,10 +808,12 @@ int batch_launch_walk(BatchSlot &S)
     // its exact modelled work; the others are one slice each.  Items of large
     // queries first, then the rest by falling work per slice.
     std::vector<double> exact(nq, 0.0);
+    std::vector<uint64_t> elements(nq, ~0ull); // |Z| of the queries with tables
     double total = 0;
     for (uint32_t k = 0; k < n_tab; ++k) {
-        const uint64_t c = S.h_totals[k];
+        const uint64_t c = S.h_totals[2 * k];
         exact[tabled[k]] = c == ~0ull ? 0.0 : (double)c; // overflow: walked not at all
+        elements[tabled[k]] = S.h_totals[2 * k + 1];
     }
     for (uint32_t i = 0; i < nq; ++i)
         if (Q[i].plan.d) total += Q[i].sliced ? exact[i] : work[i];
@@ -819,17 +828,15 @@ int batch_launch_walk(BatchSlot &S)
                           ? (uint32_t)std::min(std::max(std::ceil(work[i] / target), 1.0), 65536.0)
                           : 1;
         B2.plan.n_slices = B2.n_slices;
-        // 32-bit LDS bins: a bin moves by at most the elements of one item,
-        // and the whole query has at most work / w_el elements (exact work
-        // for a query with tables; the others are small and estimated, so
-        // with a wide margin)
-        const double el_bound = (B2.sliced ? work[i] : 128.0 * work[i]) / B2.plan.w_el;
         // 64-bit bins when half the area holds them (measured faster), else
-        // 32-bit ones under the bound, else global atomics
+        // 32-bit ones when the query has fewer than 2^30 elements (a bin of
+        // the difference array moves by at most the elements of one item;
+        // |Z| is exact from the count table, which every histogram of this
+        // size has), else global atomics
         B2.plan.hist_in_lds = 0;
         if (B2.plan.mode == FZM_HIST && B2.plan.nbins <= lds_bins / 2) B2.plan.hist_in_lds = 1;
-        else if (B2.plan.mode == FZM_HIST && B2.plan.nbins <= lds_bins &&
-                 el_bound < (double)(1u << 30))
+        else if (B2.plan.mode == FZM_HIST && B2.plan.nbins <= lds_bins && B2.sliced &&
+                 elements[i] < (1ull << 30))
             B2.plan.hist_in_lds = 2;
         B2.bound_off = n_bounds;
         n_bounds += B2.n_slices + 1;
@@ -1275,7 +1282,9 @@ const char *fz_strerror(int status)
     case FZ_EOVERFLOW: return "value out of range (n, generator or count too large)";
     case FZ_ENOMEM: return "out of device memory";
     case FZ_EDEVICE: return "HIP device error";
-    case FZ_E2BIG: return "last generator above FZ_MAX_LAST_GEN";
+    case FZ_E2BIG:
+        return "query too large (last generator above FZ_MAX_LAST_GEN, store above the "
+               "server's tuple cap, or tables above its memory budget)";
     case FZ_EINTERNAL: return "internal self-check failed";
     default: return "unknown status";
     }

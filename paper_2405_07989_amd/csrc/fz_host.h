@@ -34,7 +34,7 @@ extern std::mutex g_mu;
 // device; a server owns one per launch slot.
 struct BatchSlot {
     DevBuf meta, tables, restabs, bounds, base, recs, bins, res, cursor, totals;
-    uint64_t *h_totals = nullptr; // pinned: C[0][n] of the queries with tables
+    uint64_t *h_totals = nullptr; // pinned: C[0][n], S[0][n] of the queries with tables
     size_t h_totals_cap = 0;
     uint8_t *h_meta = nullptr;   // pinned staging of queries, jobs and items
     size_t h_meta_cap = 0;

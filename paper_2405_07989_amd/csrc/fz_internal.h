@@ -155,7 +155,7 @@ struct FzBatchBufs {
     FzSliceRec *recs;          // per item
     uint64_t *bins;            // histogram bins of hist queries
     FzBatchResult *res;        // per query
-    uint64_t *totals;          // C[0][n] of each query with tables (ids order)
+    uint64_t *totals;          // C[0][n], S[0][n] of each query with tables (ids order)
     uint32_t *cursor;          // walker item cursor (own 128-byte line)
     // optional host-visible copies (pinned, coherent): a finished query's
     // result and bins are written there and host_done[q] is set to 1 with a

@@ -470,6 +470,9 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
         c->written = 0;
     }
     if (j > W) return;
+    // a predicate's walkers may stop before taking every slice: slices
+    // nobody walks must read as empty in the totals
+    if (j < W) Bf.recs[j] = FzSliceRec{};
     Bf.base[j] = slice_bound(P, Bf.S, Bf.C, W, j, Bf.bounds + (uint64_t)j * (P.d - 2), Bf.PC);
 }
 
@@ -1174,14 +1177,15 @@ __global__ void __launch_bounds__(1024) fz_batch_dp_kernel(FzBatchBufs B, const 
     dp_query<false>(P, B.tables + Q.s_off, B.tables + Q.c_off, part, nullptr, nullptr, nullptr);
 }
 
-// Total modelled work C[0][n] of each query with tables, for the host to
-// size its slice count.
+// Total modelled work C[0][n] and element count S[0][n] of each query with
+// tables, for the host to size its slice count and its bins.
 __global__ void fz_batch_totals_kernel(FzBatchBufs B, const uint32_t *ids, uint32_t n)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const FzBatchQuery &Q = B.queries[ids[i]];
-    B.totals[i] = B.tables[Q.c_off + Q.plan.n];
+    B.totals[2 * i] = B.tables[Q.c_off + Q.plan.n];
+    B.totals[2 * i + 1] = B.tables[Q.s_off + Q.plan.n];
 }
 
 __global__ void fz_batch_restab_kernel(FzBatchBufs B)

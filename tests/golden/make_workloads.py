@@ -18,7 +18,21 @@ Choices (the readings of the workload descriptions):
                  queries; a draw is redrawn while |Z| > 1e8, or > 1e7 for a
                  store query.  Kept: each query's seed-derived redraw count
                  (fzinputs.served_query regenerates it) and |Z|.
+  batch_checks   expected results of the batch's histogram and predicate
+                 queries by enumeration (oracle.hist / oracle.exists), for
+                 every such query whose walk visits at most 3e8 prefixes
+                 (a_1..a_{d-1}).  Lengths do not depend on the coordinate
+                 order (permutation invariance is pinned on the oracle), so
+                 each set is walked with its generators in descending order,
+                 where the walk is shortest.  A histogram is kept as the
+                 SHA-256 of its bins (little-endian u64, n / min g + 1 of
+                 them) with its min and max length; a predicate as its verdict.
+
+    python tests/golden/make_workloads.py batch_checks
+
+recomputes only batch_checks (the rest of the file is kept).
 """
+import hashlib
 import json
 import os
 import sys
@@ -117,15 +131,56 @@ def served():
                 n_store=modes.count("store"))
 
 
+BATCH_CHECK_MAX_PREFIXES = 3 * 10**8
+
+
+def walk_prefixes(n, g):
+    """Prefixes (a_1..a_{d-1}) with sum a_i g_i <= n: the nested loops' work."""
+    return int(oracle.dp_series(n, g[:-1]).astype(np.float64).sum()) if len(g) > 1 else 1
+
+
+def hist_digest(bins):
+    return hashlib.sha256(np.ascontiguousarray(bins, dtype="<u8").tobytes()).hexdigest()
+
+
+def batch_checks(queries):
+    hists, preds = {}, {}
+    for i, q in enumerate(queries):
+        if q["mode"] not in ("hist", "exists"):
+            continue
+        n = q["n"]
+        g = sorted(q["g"], reverse=True)
+        if walk_prefixes(n, g) > BATCH_CHECK_MAX_PREFIXES:
+            continue
+        if q["mode"] == "hist":
+            h, lo, hi = oracle.hist(n, g)
+            assert int(h.sum()) == q["count"]
+            hists[str(i)] = dict(nbins=len(h), sha256=hist_digest(h), min_len=lo, max_len=hi)
+        else:
+            preds[str(i)] = oracle.exists(n, g, q["target_len"])
+    return dict(max_prefixes=BATCH_CHECK_MAX_PREFIXES, order="descending", hist=hists,
+                exists=preds)
+
+
 def main():
     t0 = time.time()
+    if sys.argv[1:] == ["batch_checks"]:
+        with open(OUT) as f:
+            out = json.load(f)
+        out["batch_checks"] = batch_checks(out["batch"]["queries"])
+        with open(OUT, "w") as f:
+            json.dump(out, f, separators=(",", ":"))
+        print(f"updated batch_checks in {OUT} in {time.time() - t0:.1f}s")
+        return
+    b = batch()
     out = dict(
         note="written by tests/golden/make_workloads.py from the CPU oracle; do not edit",
         single_small=single_small(),
         single_large=single_large(),
         length_set=length_set(),
-        batch=batch(),
+        batch=b,
         served=served(),
+        batch_checks=batch_checks(b["queries"]),
     )
     with open(OUT, "w") as f:
         json.dump(out, f, separators=(",", ":"))

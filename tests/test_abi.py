@@ -61,6 +61,25 @@ def test_validation_errors_without_a_device():
     assert fz._lib.fz_length_bins(10, None, 2) == 0
 
 
+def test_limit_check_does_not_wrap():
+    """n near 2^64 must be refused: n + 2 max g wraps in 64 bits, so each
+    term is bounded on its own before the sum."""
+    L = fz._lib
+    c = ctypes.c_uint64(7)
+    for n, g in [(2**64 - 2, [1, 1, 1]), (2**64 - 1500, [1000, 999, 998, 997]),
+                 (2**64 - 1, [5]), (2**63, [3, 5]), (2**32, [3, 5, 7]), (2**31, [3, 5, 7])]:
+        a, gp = _g(g)
+        assert L.fz_length_bins(n, gp, len(g)) == 0, n
+        assert L.fz_count(n, gp, len(g), ctypes.byref(c)) == fz.FZ_EOVERFLOW, n
+        assert L.fz_exists(n, gp, len(g), 1, ctypes.byref(ctypes.c_int(0))) == fz.FZ_EOVERFLOW
+        assert c.value == 7
+    # the largest accepted n still passes validation (the device call itself
+    # is what fails without a GPU)
+    a, gp = _g([3, 5, 7])
+    assert L.fz_length_bins(2**31 - 15, gp, 3) == (2**31 - 15) // 3 + 1
+    assert L.fz_length_bins(2**31 - 14, gp, 3) == 0
+
+
 def test_strerror_covers_every_status():
     for s in [0, 1, -1, -2, -3, -4, -5, -6]:
         assert fz.strerror(s) and fz.strerror(s) != "unknown status"

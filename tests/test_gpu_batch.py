@@ -5,10 +5,16 @@ query's result must be the same alone (the single-query entry points) and in
 the mix.  The 4096-query workload (d in 3..8, generators in [5,1000], n
 log-uniform in [1e3,1e6], count / histogram / predicate) is checked in full
 against the oracle's generating-function counts, and its histograms and
-predicates against the oracle where the oracle's table fits (the rest by the
-properties that hold at any size: bins sum to |Z|; a predicate that found no
-witness visited all of Z).
+predicates against the oracle bin by bin: by the oracle's bivariate
+generating function where its table is small, and by the oracle's
+enumeration (stored in tests/golden/workloads.json as a SHA-256 of the bins,
+with min and max length, and as the predicate's verdict) for every query
+whose enumeration is affordable, which covers each of the batch walker's
+bin stores (64-bit LDS bins up to 1024, 32-bit LDS bins up to 2048, global
+bins beyond).  The few largest are checked by the properties that hold at any
+size: bins sum to |Z|; a predicate that found no witness visited all of Z.
 """
+import hashlib
 import random
 
 import numpy as np
@@ -116,6 +122,71 @@ def test_workload_histograms_and_predicates(batch_result, workload):
             assert r["found"] == want, q
             checked_e += 1
     assert checked_h > 200 and checked_e > 200
+
+
+def _bin_store(nbins):
+    """The batch walker's store for a histogram of nbins bins (the rule of
+    fz_batch): 64-bit LDS bins up to 1024, 32-bit LDS bins up to 2048 (every
+    workload query has fewer than 2^30 elements), global bins beyond."""
+    return "lds64" if nbins <= 1024 else "lds32" if nbins <= 2048 else "global"
+
+
+def test_workload_against_oracle_enumeration(batch_result, workload):
+    """Bin by bin against the oracle's enumeration (tests/golden), on every
+    bin store, and predicates that found a witness against the oracle's
+    verdict."""
+    qs, res = batch_result
+    checks = fzinputs.load_golden()["batch_checks"]
+    per_store = {"lds64": 0, "lds32": 0, "global": 0}
+    big64 = found = 0
+    for key, want in checks["hist"].items():
+        i = int(key)
+        q, r = qs[i], res[i]
+        assert q["mode"] == "hist" and r["status"] == 0
+        assert len(r["bins"]) == want["nbins"], q
+        got = hashlib.sha256(np.ascontiguousarray(r["bins"], dtype="<u8").tobytes()).hexdigest()
+        assert got == want["sha256"], (i, q)
+        assert (r["min_len"], r["max_len"]) == (want["min_len"], want["max_len"]), (i, q)
+        per_store[_bin_store(want["nbins"])] += 1
+        big64 += want["nbins"] <= 1024 and (q["n"] + 1) * want["nbins"] > 3_000_000
+    for key, want in checks["exists"].items():
+        i = int(key)
+        assert qs[i]["mode"] == "exists" and res[i]["status"] == 0
+        assert res[i]["found"] == want, (i, qs[i])
+        found += want
+    assert per_store["lds32"] >= 20 and per_store["global"] >= 20 and big64 >= 20, per_store
+    assert found >= 50
+
+
+# Batch bin stores on both sides of 1024 bins (64-bit LDS bins), 2048 (32-bit
+# LDS bins) and beyond (global atomics); dense sets whose runs pile up in few
+# bins, so that 32-bit bins go negative between flushes.
+BIN_EDGES = [(3069, [3, 100, 101, 103]), (3072, [3, 100, 101, 103]),
+             (6141, [3, 100, 101, 103]), (6144, [3, 100, 101, 103]),
+             (10235, [5, 11, 13, 17]), (5115, [5, 11, 13, 17]), (5120, [5, 11, 13, 17]),
+             (10240, [5, 11, 13, 17]), (12281, [6, 11, 13, 17, 19])]
+
+
+@pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
+def test_batch_histogram_bin_stores(fz, order):
+    qs = [dict(n=n, g=g, mode="hist") for n, g in BIN_EDGES]
+    # the same queries again beside a large one, which changes the cut
+    qs += [dict(n=100000, g=[108, 86, 164, 185, 145, 65], mode="count")] + \
+          [dict(n=n, g=g, mode="hist") for n, g in BIN_EDGES]
+    assert {_bin_store(n // min(g) + 1) for n, g in BIN_EDGES} == {"lds64", "lds32", "global"}
+    try:
+        fz.config_set("walk_order", order)
+        res = fz.batch(qs)
+    finally:
+        fz.config_set("walk_order", 0)
+    for q, r in zip(qs, res):
+        assert r["status"] == 0, q
+        if q["mode"] != "hist":
+            continue
+        want = oracle.dp_hist(q["n"], q["g"])
+        assert len(r["bins"]) == len(want) and np.array_equal(r["bins"], want), (q, order)
+        nz = np.nonzero(want)[0]
+        assert (r["min_len"], r["max_len"]) == (int(nz[0]), int(nz[-1]))
 
 
 def test_alone_equals_in_the_mix(fz, batch_result, workload):
