@@ -109,6 +109,25 @@ int fz_enumerate_device(uint64_t n, const uint32_t *g, uint32_t d,
 int fz_count_stream(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
                     void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the count
+ * of fz_count_stream, by the same kernels, with no hipMalloc, hipFree or
+ * other allocation.  Every device buffer of the query (count and work tables,
+ * residue table, slice bounds and records, control block) is a piece of one
+ * fixed array of FZ_NOALLOC_SCRATCH_BYTES bytes inside the library, which
+ * each GPU holds from the first call on it until the process ends.  A query
+ * that needs more (about (2d - 3)(n + 1) 8 bytes of tables plus ~9 MB of
+ * slice data on MI355X) is refused with FZ_E2BIG (fz_last_error says how
+ * much it needed), before any device work.  The work is queued on `stream`
+ * (a hipStream_t; NULL: the device's null stream) and the call waits for it.
+ * Calls are serialized per process and each waits for its stream, so two
+ * calls never use the array at once; the array keeps the last call's
+ * contents, which the next call overwrites before reading.  Other errors as
+ * fz_count. */
+#define FZ_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fz_count_noalloc(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
+                     void *stream);
+
 /* The slice-bound primitive (Sec. 4, bounds; done here by ranks): for each
  * of the nranks ranks (0-based, host array), the element of that rank in
  * ascending lex order, row-major into the HOST buffer out[nranks][d].  A

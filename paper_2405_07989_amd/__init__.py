@@ -98,6 +98,7 @@ _vp = ctypes.c_void_p
 _SIGS = {
     "fz_count": (ctypes.c_int, [_u64, _u32p, _u32, _u64p]),
     "fz_count_stream": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _vp]),
+    "fz_count_noalloc": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _vp]),
     "fz_length_bins": (ctypes.c_uint64, [_u64, _u32p, _u32]),
     "fz_length_hist": (ctypes.c_int, [_u64, _u32p, _u32, _u64p, _u64, _u64p, _u64p]),
     "fz_exists": (ctypes.c_int, [_u64, _u32p, _u32, _u64, ctypes.POINTER(ctypes.c_int)]),
@@ -171,6 +172,20 @@ def count(n: int, g, stream=None) -> int:
         _check(_lib.fz_count(n, gp, len(arr), ctypes.byref(out)), "fz_count")
     else:
         _check(_lib.fz_count_stream(n, gp, len(arr), ctypes.byref(out), _vp(stream)), "fz_count_stream")
+    return out.value
+
+
+def count_noalloc(n: int, g, stream=None) -> int:
+    """|Z(n, g)| by fz_count_noalloc (no device allocation; the library's
+    fixed scratch array).  stream: a hipStream_t handle, None for torch's
+    current stream."""
+    arr, gp = _gens(g)
+    out = ctypes.c_uint64(0)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(_lib.fz_count_noalloc(n, gp, len(arr), ctypes.byref(out), _vp(stream)),
+           "fz_count_noalloc")
     return out.value
 
 

@@ -272,7 +272,8 @@ int make_walk_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzP
     if (rc || mode == FZM_STORE || g_walk_order == 1 || d < 2) return rc;
     uint32_t s[FZ_MAX_D];
     std::memcpy(s, g, d * sizeof(uint32_t));
-    std::stable_sort(s, s + d, [](uint32_t x, uint32_t y) { return x > y; });
+    for (uint32_t i = 1; i < d; ++i) // descending insertion sort (d <= 16)
+        for (uint32_t j = i; j > 0 && s[j - 1] < s[j]; --j) std::swap(s[j - 1], s[j]);
     if (std::equal(s, s + d, g)) return FZ_OK;
     FzPlan Q;
     if (make_plan(n, s, d, mode, &Q)) return FZ_OK; // keep the caller's order
@@ -319,14 +320,15 @@ struct Launch {
     uint32_t nwg;
 };
 
-// Sizes the scratch for plan P and fills the buffer table.
-int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
+// Slice count, walker grid and walker variant of plan P on a device with
+// `cus` compute units (no allocation).
+void plan_launch(int cus, FzPlan &P, Launch &L)
 {
     const uint32_t wgcu = g_wg_per_cu ? g_wg_per_cu : kDefaultWgPerCu;
     const uint32_t spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
-    const uint64_t waves = (uint64_t)c.cus * wgcu * (FZK_WG / FZK_WAVE);
+    const uint64_t waves = (uint64_t)cus * wgcu * (FZK_WG / FZK_WAVE);
     P.n_slices = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(waves * spw, 1), kMaxSlices);
-    L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)c.cus * wgcu,
+    L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)cus * wgcu,
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
     P.hist_in_lds = (P.mode == FZM_HIST) &&
                     ((size_t)P.nbins * 8 <= kLdsHistBudget); // one set per workgroup
@@ -334,19 +336,34 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     P.pair = worth_pair(P) ? 1 : 0;
     if (P.pair && g_prune_mode != 2) P.prune = 1; // the pair walker skips empty rows too
     if (P.d < 4) P.prune = P.pair = 0;
-    const uint64_t table_words = (uint64_t)(P.d - 1) * P.stride;
-    const uint64_t cost_words = (uint64_t)(P.d - 2) * P.stride;
-    FZ_TRY(ensure(c.S, table_words * 8));
-    FZ_TRY(ensure(c.C, cost_words * 8));
-    FZ_TRY(ensure(c.restab, (size_t)2 * P.B * sizeof(int2)));
-    FZ_TRY(ensure(c.bounds, (size_t)(P.n_slices + 1) * (P.d - 2) * 4));
-    FZ_TRY(ensure(c.base, (size_t)(P.n_slices + 1) * 8));
-    FZ_TRY(ensure(c.recs, (size_t)P.n_slices * sizeof(FzSliceRec)));
-    FZ_TRY(ensure(c.ctl, sizeof(FzCtl)));
-    FZ_TRY(ensure(c.dpart, (size_t)FZK_DP_UNITS * 8));
+}
+
+// Bytes of each device buffer a single query of plan P needs.
+struct ScratchSizes {
+    size_t S, C, restab, bounds, base, recs, ctl, dpart, pt, hist, hist_rows;
+};
+
+ScratchSizes scratch_sizes(const FzPlan &P, const Launch &L)
+{
+    ScratchSizes z;
+    z.S = (size_t)(P.d - 1) * P.stride * 8;
+    z.C = (size_t)(P.d - 2) * P.stride * 8;
+    z.restab = (size_t)2 * P.B * sizeof(int2);
+    z.bounds = (size_t)(P.n_slices + 1) * (P.d - 2) * 4;
+    z.base = (size_t)(P.n_slices + 1) * 8;
+    z.recs = (size_t)P.n_slices * sizeof(FzSliceRec);
+    z.ctl = sizeof(FzCtl);
+    z.dpart = (size_t)FZK_DP_UNITS * 8;
+    z.pt = P.pair ? (size_t)pair_words(P) * 8 : 0;
+    z.hist = P.mode == FZM_HIST ? (size_t)P.nbins * 8 : 0;
+    z.hist_rows = (P.mode == FZM_HIST && P.hist_in_lds) ? (size_t)L.nwg * P.nbins * 8 : 0;
+    return z;
+}
+
+void bind_pair(const FzPlan &P, uint64_t *pt, FzBufs &B)
+{
     if (P.pair) {
-        FZ_TRY(ensure(c.pt, pair_words(P) * 8));
-        B.PC = (uint64_t *)c.pt.p;
+        B.PC = pt;
         B.PE = (uint32_t *)(B.PC + P.stride);
         B.PO = B.PE + 2 * ((P.stride + 1) / 2);
     } else {
@@ -354,9 +371,26 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
         B.PE = nullptr;
         B.PO = nullptr;
     }
+}
+
+// Sizes the scratch for plan P and fills the buffer table.
+int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
+{
+    plan_launch(c.cus, P, L);
+    const ScratchSizes z = scratch_sizes(P, L);
+    FZ_TRY(ensure(c.S, z.S));
+    FZ_TRY(ensure(c.C, z.C));
+    FZ_TRY(ensure(c.restab, z.restab));
+    FZ_TRY(ensure(c.bounds, z.bounds));
+    FZ_TRY(ensure(c.base, z.base));
+    FZ_TRY(ensure(c.recs, z.recs));
+    FZ_TRY(ensure(c.ctl, z.ctl));
+    FZ_TRY(ensure(c.dpart, z.dpart));
+    if (P.pair) FZ_TRY(ensure(c.pt, z.pt));
+    bind_pair(P, (uint64_t *)c.pt.p, B);
     if (P.mode == FZM_HIST) {
-        FZ_TRY(ensure(c.hist, (size_t)P.nbins * 8));
-        if (P.hist_in_lds) FZ_TRY(ensure(c.hist_rows, (size_t)L.nwg * P.nbins * 8));
+        FZ_TRY(ensure(c.hist, z.hist));
+        if (P.hist_in_lds) FZ_TRY(ensure(c.hist_rows, z.hist_rows));
     }
     B.S = (uint64_t *)c.S.p;
     B.C = (uint64_t *)c.C.p;
@@ -969,6 +1003,105 @@ int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
     return FZ_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Allocation-free count (fz_count_noalloc).  The count path of
+// fz_count_stream, with every device buffer carved from one fixed array of
+// this file instead of the library's grow-only buffers.  In host code the
+// array's name only stands for the symbol: its device address is looked up
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is ever passed to kernels.  Every call on a device reuses the
+// same array and leaves its contents behind; the walk rewrites every word it
+// reads (tables, bounds, control block and slice records are written by the
+// kernels before use), so nothing needs clearing.  Calls are serialized per
+// process and wait for their stream, so two calls never overlap on the array.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[FZ_NOALLOC_SCRATCH_BYTES];
+
+struct NoAllocDev {
+    bool ready = false;
+    int cus = 0;
+    uint8_t *ptr = nullptr; // device address of `scratch` on this device
+};
+NoAllocDev g_noalloc[kMaxDevices];
+
+int noalloc_device(NoAllocDev **out)
+{
+    (void)hipGetLastError();
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        (void)hipGetLastError();
+        return dev_err_at(e == hipSuccess ? hipErrorInvalidDevice : e, "hipGetDevice", __LINE__);
+    }
+    NoAllocDev &a = g_noalloc[dev];
+    if (!a.ready) {
+        int cus = 0;
+        FZ_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        void *ptr = nullptr;
+        FZ_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (ptr == nullptr) return dev_err_at(hipErrorInvalidSymbol, "hipGetSymbolAddress", __LINE__);
+        a.cus = cus;
+        a.ptr = (uint8_t *)ptr;
+        a.ready = true;
+    }
+    *out = &a;
+    return FZ_OK;
+}
+
+int do_count_noalloc(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count, void *stream)
+{
+    if (count == nullptr) return FZ_EINVAL;
+    FzPlan P;
+    int rc = make_walk_plan(n, g, d, FZM_COUNT, &P);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    NoAllocDev *a;
+    if ((rc = noalloc_device(&a))) return rc;
+    Launch L;
+    plan_launch(a->cus, P, L);
+    const ScratchSizes z = scratch_sizes(P, L);
+    // 256-byte aligned pieces of the array, in a fixed order
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += (std::max<size_t>(bytes, 8) + 255) & ~(size_t)255;
+        return a->ptr + o;
+    };
+    FzBufs B;
+    std::memset(&B, 0, sizeof B);
+    B.S = (uint64_t *)take(z.S);
+    B.C = (uint64_t *)take(z.C);
+    B.restab = (int2 *)take(z.restab);
+    B.bounds = (uint32_t *)take(z.bounds);
+    B.base = (uint64_t *)take(z.base);
+    B.recs = (FzSliceRec *)take(z.recs);
+    B.ctl = (FzCtl *)take(z.ctl);
+    B.dpart = (uint64_t *)take(z.dpart);
+    uint64_t *pt = P.pair ? (uint64_t *)take(z.pt) : nullptr;
+    if (off > (size_t)FZ_NOALLOC_SCRATCH_BYTES) {
+        std::snprintf(g_err_msg, sizeof g_err_msg,
+                      "fz_count_noalloc: the query needs %zu bytes of device scratch, the fixed "
+                      "array holds %zu (FZ_NOALLOC_SCRATCH_BYTES)",
+                      off, (size_t)FZ_NOALLOC_SCRATCH_BYTES);
+        return FZ_E2BIG;
+    }
+    bind_pair(P, pt, B);
+    const hipStream_t s = (hipStream_t)stream;
+    FZ_TRY(fzk_launch_dp(P, B, s));
+    FZ_TRY(fzk_launch_restab(P, B, s));
+    FZ_TRY(fzk_launch_slices(P, B, s));
+    FZ_TRY(fzk_launch_enum(P, B, L.nwg, s));
+    FZ_TRY(fzk_launch_finalize(P, B, L.nwg, s));
+    FzCtl h;
+    FZ_TRY(hipMemcpyAsync(&h, B.ctl, sizeof(FzCtl), hipMemcpyDeviceToHost, s));
+    FZ_TRY(hipStreamSynchronize(s));
+    if (h.status & FZS_OVERFLOW) return FZ_EOVERFLOW;
+    if ((h.status & FZS_MISMATCH) || h.count != h.total) return FZ_EINTERNAL;
+    *count = h.count;
+    return FZ_OK;
+}
+
 } // namespace fzh
 
 using namespace fzh;
@@ -991,6 +1124,11 @@ int fz_count(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count)
 int fz_count_stream(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count, void *stream)
 {
     return do_count(n, g, d, count, stream);
+}
+
+int fz_count_noalloc(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count, void *stream)
+{
+    return do_count_noalloc(n, g, d, count, stream);
 }
 
 uint64_t fz_length_bins(uint64_t n, const uint32_t *g, uint32_t d)
