@@ -76,30 +76,55 @@ def measured_traffic():
     return {k: float(v) for k, v in vals.items() if k.endswith("_bytes")}
 
 
-def cpu_baseline(n, g, seconds_target=15.0):
-    """The oracle's ascending walk on the lex-smallest elements of the same
-    query (count consumer, then store consumer), one host core."""
-    import oracle
-    import numpy as np  # noqa: F401
+def host_threads():
+    """Host cores this process may use: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (a GPU machine's share of its host)."""
+    n = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(omp))) if omp.isdigit() and int(omp) > 0 else n
 
-    k = 2_000_000
+
+def cpu_baseline(n, g, N, cpu_seconds=20.0, windows=256):
+    """The oracle's plain ascending walk, timed on windows spread over the
+    whole set: window j starts at the element of rank about j N / windows
+    (from the oracle's own unranking) and walks k elements from there, 3/4 of
+    the windows with the count consumer and 1/4 with the store consumer.  The
+    windows run on every host core this process has (one walk per thread;
+    the C oracle releases the interpreter lock), sized to about cpu_seconds
+    of single-core work; the single-core rate on the first windows is
+    reported beside it."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+
+    starts = [oracle.unrank_dp(n, g, (j * N) // windows + (N // windows) // 2)
+              for j in range(windows)]
+    # single-core rate on a few windows of 1e6 elements
     t0 = time.perf_counter()
-    oracle.walk(n, g, stop_after=k)
+    probe = 0
+    for j in range(0, windows, windows // 4):
+        probe += oracle.walk(n, g, start=starts[j], stop_after=10**6)["count"]
+    single_rate = probe / (time.perf_counter() - t0)
+    k = max(10**5, int(single_rate * cpu_seconds / windows))
+
+    def one(j):
+        if j % 4 == 3:
+            return len(oracle.walk(n, g, start=starts[j], stop_after=k, out_cap=k)["store"])
+        return oracle.walk(n, g, start=starts[j], stop_after=k)["count"]
+
+    threads = host_threads()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        got = list(ex.map(one, range(windows)))
     dt = time.perf_counter() - t0
-    # scale the sample to about seconds_target of CPU time, split count/store
-    k_count = max(k, int(k * (0.6 * seconds_target) / max(dt, 1e-3)))
-    k_store = max(k, int(k * (0.4 * seconds_target) / max(dt, 1e-3)) // 2)
-    t0 = time.perf_counter()
-    c = oracle.walk(n, g, stop_after=k_count)["count"]
-    t1 = time.perf_counter()
-    s = oracle.walk(n, g, stop_after=k_store, out_cap=k_store)["store"]
-    t2 = time.perf_counter()
-    assert c == k_count and len(s) == k_store
-    rate = (k_count + k_store) / (t2 - t0)
-    return dict(value=rate, unit="factorizations/s", cores=1, kind="oracle",
-                sample=(f"lex-smallest {k_count} elements (count consumer, {t1 - t0:.1f}s) + "
-                        f"lex-smallest {k_store} elements (store consumer, {t2 - t1:.1f}s) "
-                        f"of the same d=6 query, single-threaded C oracle"))
+    total = sum(got)
+    assert all(x == k for x in got[:-1])  # every window but the last holds k elements
+    return dict(value=total / dt, unit="factorizations/s", cores=threads, kind="oracle",
+                single_core_value=single_rate,
+                sample=(f"{windows} windows of {k} elements each, starting at ranks "
+                        f"(j + 1/2) |Z| / {windows} of the same d=6 query (3/4 count consumer, "
+                        f"1/4 store consumer), {total} elements in {dt:.1f} s on {threads} "
+                        f"threads; C oracle, plain ascending nested loops"))
 
 
 def percentile(v, p):
@@ -141,6 +166,36 @@ def measure_batch(fz, reps=3):
             "prep_ms": sorted(prep)[len(prep) // 2], "walk_ms": sorted(walk)[len(walk) // 2],
             "workload": "4096 queries: d in 3..8, generators in [5,1000], n log-uniform in "
                         "[1e3,1e6], |Z| <= 1e8, consumer count/hist/exists"}
+
+
+def measure_single_small(fz, torch, reps=200):
+    """End-to-end latency of the small single query (g = (11,13,17,23),
+    n = 10000, |Z| = 3,009,519), host call to host return: the count, and
+    the store of all its rows into a preallocated device tensor (48 MB)."""
+    import fzinputs
+    w = fzinputs.load_golden()["single_small"]
+    n, g, N = w["n"], w["g"], w["count"]
+    out = torch.empty((N, len(g)), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    res = {"workload": f"g={g} n={n}: count |Z|={N}; store all {N} rows ({N * len(g) * 4} B)"}
+    for mode in ("count", "store"):
+        lat = []
+        for r in range(reps + 10):
+            t0 = time.perf_counter()
+            if mode == "count":
+                ok = fz.count(n, g) == N
+            else:
+                ok = fz.enumerate_device(n, g, out) == (N, N)
+            dt = time.perf_counter() - t0
+            if not ok:
+                raise RuntimeError(f"single small query: wrong {mode} result")
+            if r >= 10:
+                lat.append(dt)
+        res[f"{mode}_p50_us"] = percentile(lat, 0.5) * 1e6
+        res[f"{mode}_p99_us"] = percentile(lat, 0.99) * 1e6
+        res[f"{mode}_factorizations_per_s"] = N / percentile(lat, 0.5)
+    del out
+    return res
 
 
 def _serve(fz, qs, gaps=None, inflight=4):
@@ -413,6 +468,9 @@ def main():
         "walker_stats": st_ls,
     }
     log("length-set histogram done")
+    res["single_small"] = measure_single_small(fz, torch)
+    log("single small query: count p50 %.0f us, store p50 %.0f us" % (
+        res["single_small"]["count_p50_us"], res["single_small"]["store_p50_us"]))
     del out
     torch.cuda.empty_cache()
     if args.calibrate_copy:
@@ -436,7 +494,7 @@ def main():
         res["store_roofline"]["traffic"] = tr.get("store_walker_bytes")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(n, g)
+        res["cpu_baseline"] = cpu_baseline(n, g, N)
         log("cpu baseline done")
     print(json.dumps(res), flush=True)
 

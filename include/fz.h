@@ -266,7 +266,11 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * with d >= 4: 0: when the last pair represents few remainders, about
  * n D / (2 A B) < 1/4, rows walk only the remainders it represents, listed
  * per residue chain from the count table, and skip empty rows too; 1:
- * always; 2: never; batches never use it).  FZ_EINVAL for an
+ * always; 2: never; batches never use it), "min_slice_work" (single
+ * queries: a query whose whole modelled work is small is cut into fewer
+ * slices, each carrying at least this much work, so that it occupies a few
+ * wavefronts briefly; default 65536, about a thousand wavefront
+ * instructions; 1: always the full slice count).  FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */
 int fz_config_set(const char *key, int64_t value);

@@ -23,6 +23,9 @@ constexpr int kMaxDevices = 64;
 constexpr uint32_t kDefaultSlicesPerWave = 16;
 constexpr uint32_t kDefaultWgPerCu = 8;
 constexpr uint32_t kMaxSlices = 1u << 22;
+// Least modelled work of a single query's slice (1/64 wave instructions):
+// about a thousand wave instructions, a few microseconds.
+constexpr uint64_t kMinSliceWork = 1u << 16;
 constexpr size_t kLdsHistBudget = 64 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
 // per-wave LDS histogram in batches, 8 KB per wave: 1024 64-bit bins, or
@@ -68,6 +71,7 @@ uint32_t g_prune_mode = 0; // 0: by the set's density, 1: always, 2: never
 uint32_t g_walk_order = 0; // 0: descending for order-free consumers, 1: the caller's
 uint32_t g_batch_graph = 1; // batch phase 2 as a HIP graph (1) or plain launches (0)
 uint32_t g_pair_mode = 0;   // pair table: 0 by sparsity of the last pair, 1 always, 2 never
+uint64_t g_min_slice_work = 0; // 0: kMinSliceWork
 
 bool worth_pruning(const FzPlan &P);
 bool worth_pair(const FzPlan &P);
@@ -328,6 +332,7 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
     const uint32_t spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
     const uint64_t waves = (uint64_t)cus * wgcu * (FZK_WG / FZK_WAVE);
     P.n_slices = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(waves * spw, 1), kMaxSlices);
+    P.min_slice_work = g_min_slice_work ? g_min_slice_work : kMinSliceWork;
     L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)cus * wgcu,
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
     P.hist_in_lds = (P.mode == FZM_HIST) &&
@@ -423,7 +428,7 @@ int run_query(Ctx &c, FzPlan &P, FzBufs &B, const Launch &L, hipStream_t s)
     const FzCtl &h = *c.host_ctl;
     if (h.status & FZS_OVERFLOW) return FZ_EOVERFLOW;
     if (h.status & FZS_MISMATCH) return FZ_EINTERNAL;
-    c.last.slices = P.n_slices;
+    c.last.slices = h.slices;
     c.last_batch = false;
     c.last.rows = h.rows;
     c.last.prefixes = h.prefixes;
@@ -1292,6 +1297,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "walk_order") == 0 && value <= 1) g_walk_order = (uint32_t)value;
     else if (std::strcmp(key, "batch_graph") == 0 && value <= 1) g_batch_graph = (uint32_t)value;
     else if (std::strcmp(key, "pair_table") == 0 && value <= 2) g_pair_mode = (uint32_t)value;
+    else if (std::strcmp(key, "min_slice_work") == 0) g_min_slice_work = (uint64_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

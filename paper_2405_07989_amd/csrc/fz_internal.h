@@ -59,6 +59,7 @@ struct FzPlan {
     uint32_t stride;     // n + 1: row length of the count table
     uint64_t target_len; // predicate target
     uint64_t max_tuples; // store limit; UINT64_MAX for the other consumers
+    uint64_t min_slice_work; // single query: least modelled work of a slice (0: always W)
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag
@@ -69,7 +70,7 @@ struct FzCtl {
     uint32_t found;
     uint32_t pad1[31];
     uint32_t status;     // FZS_* bits
-    uint32_t pad2;
+    uint32_t slices;     // slices cut: W, or fewer for a small query
     uint64_t total;      // |Z| from the count table
     uint64_t count;      // elements the walkers visited
     uint64_t rows, prefixes;

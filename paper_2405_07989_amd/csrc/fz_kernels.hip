@@ -452,10 +452,21 @@ __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64
     return base;
 }
 
+// Slices of a single query: W = P.n_slices, or fewer when the query's whole
+// modelled work C[0][n] is small, so that every slice carries at least
+// P.min_slice_work (a small query then occupies a few waves briefly instead
+// of every wave of the chip).  Every thread computes the same value.
+__device__ __forceinline__ uint32_t cut_slices(const FzPlan &P, const uint64_t *C)
+{
+    if (P.min_slice_work == 0) return P.n_slices;
+    const uint64_t k = C[P.n] / P.min_slice_work + 1;
+    return k < P.n_slices ? (uint32_t)k : P.n_slices;
+}
+
 __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
 {
     const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t W = P.n_slices;
+    const uint32_t W = cut_slices(P, Bf.C);
     if (j == 0) {
         const uint64_t N = Bf.S[P.n];
         const bool ovf = (N == ~0ull) || (Bf.C[P.n] == ~0ull);
@@ -463,6 +474,7 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
         c->cursor = 0;
         c->found = 0;
         c->status = ovf ? FZS_OVERFLOW : 0u;
+        c->slices = W;
         c->total = N;
         c->count = 0;
         c->rows = 0;
@@ -620,6 +632,29 @@ __device__ __forceinline__ bool skip_empty(const FzPlan &P, const uint32_t M, co
     }
 }
 
+// The element loop of a dense walk: two candidate steps per trip (ad >= 0,
+// ad >= delta: one element each), then ad -= 2 delta, while some lane's next
+// step is valid.  Written out so that each trip is five vector instructions
+// and one branch: the validity test of a step is the carry into the count.
+// Every lane of the wave must be active.
+__device__ __forceinline__ void count_steps(uint32_t &cnt, int32_t &ad, int32_t delta,
+                                            int32_t delta2)
+{
+    asm volatile("v_cmp_le_i32 vcc, 0, %1\n"
+                 "s_cbranch_vccz 2f\n"
+                 "1:\n"
+                 "v_addc_co_u32 %0, vcc, 0, %0, vcc\n"
+                 "v_cmp_le_i32 vcc, %2, %1\n"
+                 "v_addc_co_u32 %0, vcc, 0, %0, vcc\n"
+                 "v_subrev_u32 %1, %3, %1\n"
+                 "v_cmp_le_i32 vcc, 0, %1\n"
+                 "s_cbranch_vccnz 1b\n"
+                 "2:\n"
+                 : "+v"(cnt), "+v"(ad)
+                 : "s"(delta), "s"(delta2)
+                 : "vcc");
+}
+
 // FIXED: M == MAXM (a compile-time depth: the single-query walker), which
 // allows the row fast paths below without per-level selects.
 template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED>
@@ -642,12 +677,16 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
     const uint32_t c64r = g2r64 - c64r0q * P.B;
     const uint32_t len_step = P.ord - P.delta;
     const int32_t delta = (int32_t)P.delta;
+    const int32_t delta2 = 2 * delta; // two candidate steps
     // lengths are < 2^31, so a target beyond 32 bits matches none
     const uint32_t target = P.target_len >> 32 ? FZK_SENTINEL : (uint32_t)P.target_len;
     // per-lane element counters: a chunk adds at most n + 1 per lane to the
     // 32-bit counter, which is folded into the 64-bit one per chunk
     uint64_t lane_el = 0;
     uint32_t lane_pref = 0;
+    uint64_t lane_pref64 = 0; // lane prefixes of the rows of the block walk
+    // BLOCKS: a compile-time depth and no row skipping (see the block walk)
+    constexpr bool BLOCKS = FIXED && !PRUNE && !PAIR && MAXM > 0;
     uint64_t n_el = 0, n_rows = 0;
     if (uni(b0[0]) != FZK_SENTINEL) {
         uint32_t a[MAXM > 0 ? MAXM : 1];
@@ -689,7 +728,236 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
         };
         bool upper_eq = FIXED ? upper_equal() : false;
         bool done = false;
-        while (!done) {
+        // One chunk of lane prefixes: lane l has x = xl, the first valid
+        // a[d-2] = t0 and a[d-1] = ad0 there (-1: no element).  For the
+        // store, the x of position j's owner is xbase + j, or s_x[j] when
+        // the lanes' x are not consecutive.  Returns true to stop the walk.
+        auto consume = [&](const uint32_t xl, const uint32_t t0, int32_t ad0, const int32_t xbase,
+                           const bool x_in_lds) -> bool {
+            uint32_t cnt = 0;
+            if constexpr (MODE == FZM_COUNT) {
+                // two candidate steps per trip; a trip runs while some
+                // lane's next step is valid (no trip that finds nothing).
+                // Dense walks enter the loop at once (almost every chunk has
+                // an element); the others test first.
+                int32_t ad = ad0;
+                if constexpr (BLOCKS) {
+                    count_steps(cnt, ad, delta, delta2);
+                } else if (__ballot(ad >= 0)) {
+                    do {
+                        cnt += ad >= 0 ? 1u : 0u;
+                        cnt += ad >= delta ? 1u : 0u;
+                        ad -= delta2;
+                    } while (__ballot(ad >= 0));
+                }
+                lane_el += cnt;
+            } else if constexpr (MODE == FZM_HIST) {
+                // The lane's elements are counted one by one as in the
+                // count consumer; their lengths step by len_step, so the
+                // run is then recorded as a strided difference (finalize
+                // integrates along the stride).
+                int32_t ad = ad0;
+                if constexpr (BLOCKS) {
+                    count_steps(cnt, ad, delta, delta2);
+                } else if (__ballot(ad >= 0)) {
+                    do {
+                        cnt += ad >= 0 ? 1u : 0u;
+                        cnt += ad >= delta ? 1u : 0u;
+                        ad -= delta2;
+                    } while (__ballot(ad >= 0));
+                }
+                lane_el += cnt;
+                if (cnt) {
+                    const uint32_t len0 = plen + xl + t0 + (uint32_t)ad0;
+                    hist_run(P, io, len0, cnt, (int32_t)len_step);
+                }
+            } else if constexpr (MODE == FZM_EXISTS) {
+                // each element's length is compared with the target; the
+                // wave looks at the lanes' verdicts once per chunk
+                int32_t ad = ad0;
+                uint32_t len = plen + xl + t0 + (uint32_t)ad0;
+                bool hit = false;
+                if (BLOCKS || __ballot(ad >= 0)) {
+                    do {
+                        const bool c0 = ad >= 0;
+                        const bool c1 = ad >= delta;
+                        cnt += c0 ? 1u : 0u;
+                        cnt += c1 ? 1u : 0u;
+                        hit = hit || (c0 && len == target) || (c1 && len + len_step == target);
+                        ad -= delta2;
+                        len += 2 * len_step;
+                    } while (__ballot(ad >= 0));
+                }
+                lane_el += cnt;
+                if (__ballot(hit)) {
+                    __hip_atomic_store(io.found, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    return true;
+                }
+            } else { // FZM_STORE
+                uint64_t L = 0;
+                if (ad0 >= 0) L = fdiv((uint32_t)ad0, P.div_delta) + 1;
+                const uint64_t incl = wave_incl_scan64(L, lane);
+                const uint64_t T = readlane64(incl, FZK_WAVE - 1);
+                io.s_incl[lane] = incl;
+                io.s_t0[lane] = t0;
+                io.s_ad0[lane] = (uint32_t)ad0;
+                if (x_in_lds) io.s_x[lane] = xl;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                // Rows are produced 64 at a time (lane = position in the
+                // chunk's output), staged in LDS as one contiguous block
+                // and written out as consecutive dwords: every store
+                // instruction covers 256 bytes.
+                const uint64_t lim = P.max_tuples;
+                const uint32_t du = P.d_user;
+                for (uint64_t p0 = 0; p0 < T && rank + p0 < lim; p0 += FZK_WAVE) {
+                    const uint64_t left = T - p0 < lim - rank - p0 ? T - p0 : lim - rank - p0;
+                    const uint32_t nb = left < FZK_WAVE ? (uint32_t)left : FZK_WAVE;
+                    const uint64_t p = p0 + lane;
+                    if (lane < nb) {
+                        uint32_t j = 0;
+#pragma unroll
+                        for (uint32_t st = FZK_WAVE / 2; st >= 1; st >>= 1)
+                            if (io.s_incl[j + st - 1] <= p) j += st;
+                        const uint32_t k = (uint32_t)(p - (j ? io.s_incl[j - 1] : 0ull));
+                        // coordinates a[0..M-1], x, t, ad; the first pad
+                        // (virtual) coordinates are not output
+                        uint32_t *st_row = io.s_stage + lane * du;
+#pragma unroll
+                        for (int q = 0; q < MAXM; ++q)
+                            if (q < (int)M && (uint32_t)q >= P.pad) st_row[q - P.pad] = a[q];
+                        if (M >= P.pad)
+                            st_row[M - P.pad] = x_in_lds ? io.s_x[j] : (uint32_t)xbase + j;
+                        if (M + 1 >= P.pad) st_row[M + 1 - P.pad] = io.s_t0[j] + k * P.ord;
+                        st_row[M + 2 - P.pad] = io.s_ad0[j] - k * P.delta;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                    uint32_t *dst = io.out + (rank + p0) * du;
+                    const uint32_t words = nb * du;
+                    for (uint32_t i = lane; i < words; i += FZK_WAVE) dst[i] = io.s_stage[i];
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (rank < lim) n_el += (T < lim - rank) ? T : (lim - rank);
+                rank += T;
+                if (rank >= lim) return true;
+            }
+            return false;
+        };
+
+        // BLOCKS (a compile-time depth, no row skipping): the rows of the
+        // deepest row level are prepared up to 64 at a time, one per lane --
+        // the row's last x and its first chunk's remainder split Rc = Qc B +
+        // Pc -- and walked one by one, each read with readlane, so a row
+        // costs the scalar unit only its loop step.  Within a row each lane
+        // keeps its own table index rho = Pc + lr2 and quotient q = Qc - lq1
+        // and steps them by 64 G2 per chunk (a borrow when rho drops below
+        // lr2): the chunk loop is vector work but for its one branch.
+        if constexpr (BLOCKS) {
+            const uint32_t gy = P.g[MAXM > 0 ? MAXM - 1 : 0];
+            for (;;) {
+                // rows y = a[M-1] + lane while in the set and in the slice
+                const uint32_t ay = a[MAXM - 1];
+                const uint32_t R0 = rr[MAXM];
+                const uint64_t off = (uint64_t)lane * gy;
+                bool in = off <= R0;
+                if (upper_eq) in = in && ay + lane <= e[MAXM - 1];
+                const uint32_t nb = (uint32_t)__builtin_popcountll(__ballot(in));
+                const bool blast = upper_eq && ay + nb - 1 == e[MAXM - 1];
+                const uint32_t R = R0 - (uint32_t)off; // meaningful for lanes in
+                const uint32_t x0 = lane == 0 ? (uint32_t)xs : 0u;
+                const int32_t xlast =
+                    (blast && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
+                // the row's lane prefixes x0..xlast (rows of a stopped walk
+                // count in full)
+                const int32_t v_np = in && xlast >= (int32_t)x0 ? xlast - (int32_t)x0 + 1 : 0;
+                lane_pref64 += (uint32_t)v_np;
+                const uint32_t v_Rc = R - x0 * P.G2;
+                const uint32_t v_Qc = fdiv(v_Rc, P.div_B);
+                const uint32_t v_Pc = v_Rc - v_Qc * P.B;
+                const uint32_t plen0 = plen;
+                uint32_t j = 0;
+                for (; j < nb; ++j) {
+                    const int32_t np = (int32_t)__builtin_amdgcn_readlane((uint32_t)v_np, j);
+                    const uint32_t Qc = __builtin_amdgcn_readlane(v_Qc, j);
+                    const uint32_t Pc = __builtin_amdgcn_readlane(v_Pc, j);
+                    // the count does not look at x
+                    const int32_t xf = MODE == FZM_COUNT ? 0 : (j == 0 ? xs : 0);
+                    a[MAXM - 1] = ay + j;
+                    plen = plen0 + j;
+                    if constexpr (MODE == FZM_EXISTS) {
+                        const uint32_t f = __hip_atomic_load(io.found, __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                        if (uni(f)) {
+                            done = true;
+                            break;
+                        }
+                    }
+                    uint32_t rho = Pc + lr2;          // in [lr2, lr2 + B), inside the 2B table
+                    int32_t q = (int32_t)(Qc - lq1);
+                    int32_t c = xf;
+                    for (int32_t left = np - 1; left >= 0; left -= FZK_WAVE, c += FZK_WAVE) {
+                        const bool active = (int32_t)lane <= left;
+                        const int2 ent = TLDS ? io.ltab[rho] : io.gtab[rho];
+                        int32_t ad0 = q - ent.y;
+                        ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                        if (consume((uint32_t)c + lane, (uint32_t)ent.x, ad0, c, false)) {
+                            done = true;
+                            break;
+                        }
+                        rho -= c64r;
+                        q -= (int32_t)c64q;
+                        if ((int32_t)rho < (int32_t)lr2) {
+                            rho += P.B;
+                            q -= 1;
+                        }
+                    }
+                    if (done) break;
+                }
+                n_rows += j < nb ? j + 1 : nb;
+                if (done || blast) break;
+                // the block's last row, then the next row of the deepest
+                // level, else of a shallower one
+                a[MAXM - 1] = ay + nb - 1;
+                rr[MAXM] = R0 - (nb - 1) * gy;
+                plen = plen0 + nb - 1;
+                xs = 0;
+                if (rr[MAXM] >= gy) {
+                    a[MAXM - 1] += 1;
+                    rr[MAXM] -= gy;
+                    plen += 1;
+                    continue;
+                }
+                int kk = -1;
+#pragma unroll
+                for (int k = 0; k + 1 < MAXM; ++k)
+                    if (rr[k + 1] >= P.g[k]) kk = k;
+                if (kk < 0) break;
+#pragma unroll
+                for (int k = 0; k < MAXM; ++k) {
+                    if (k == kk) {
+                        a[k] += 1;
+                        rr[k + 1] -= P.g[k];
+                    } else if (k > kk) {
+                        a[k] = 0;
+                        rr[k + 1] = rr[k];
+                    }
+                }
+                plen = 0;
+#pragma unroll
+                for (int k = 0; k < MAXM; ++k) plen += a[k];
+                upper_eq = upper_equal();
+            }
+        }
+        while (!BLOCKS && !done) {
             if (PRUNE && M > 0) {
                 bool moved = false;
                 if (!skip_empty<MAXM>(P, M, io.S, a, rr, e, end_open, chk, moved, lane)) break;
@@ -710,13 +978,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 if constexpr (MAXM > 0) last = upper_eq && a[MAXM - 1] == e[MAXM - 1];
                 else last = upper_eq;
             } else if (!end_open) {
-                bool deep = true;
-                if constexpr (FIXED && MAXM > 0) deep = a[MAXM - 1] == e[MAXM - 1];
-                if (deep) {
-                    last = true;
+                last = true;
 #pragma unroll
-                    for (int k = 0; k < MAXM; ++k) last = last && (k >= (int)M || a[k] == e[k]);
-                }
+                for (int k = 0; k < MAXM; ++k) last = last && (k >= (int)M || a[k] == e[k]);
             }
             const int32_t xlast = last ? xe - 1 : xhi;
             ++n_rows;
@@ -725,125 +989,6 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     __hip_atomic_load(io.found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (uni(f)) break;
             }
-            // One chunk of lane prefixes: lane l has x = xl, the first valid
-            // a[d-2] = t0 and a[d-1] = ad0 there (-1: no element).  For the
-            // store, the x of position j's owner is xbase + j, or s_x[j] when
-            // the lanes' x are not consecutive.  Returns true to stop the walk.
-            auto consume = [&](const uint32_t xl, const uint32_t t0, int32_t ad0, const int32_t xbase,
-                               const bool x_in_lds) -> bool {
-                uint32_t cnt = 0;
-                if constexpr (MODE == FZM_COUNT) {
-                    // two candidate steps per trip; the trip test is the
-                    // first step's own validity test
-                    int32_t ad = ad0;
-                    for (;;) {
-                        const bool c0 = ad >= 0;
-                        if (!__ballot(c0)) break;
-                        const bool c1 = ad >= delta;
-                        cnt += c0 ? 1u : 0u;
-                        cnt += c1 ? 1u : 0u;
-                        ad -= 2 * delta;
-                    }
-                    lane_el += cnt;
-                } else if constexpr (MODE == FZM_HIST) {
-                    // The lane's elements are counted one by one as in the
-                    // count consumer; their lengths step by len_step, so the
-                    // run is then recorded as a strided difference (finalize
-                    // integrates along the stride).
-                    int32_t ad = ad0;
-                    for (;;) {
-                        const bool c0 = ad >= 0;
-                        if (!__ballot(c0)) break;
-                        const bool c1 = ad >= delta;
-                        cnt += c0 ? 1u : 0u;
-                        cnt += c1 ? 1u : 0u;
-                        ad -= 2 * delta;
-                    }
-                    lane_el += cnt;
-                    if (cnt) {
-                        const uint32_t len0 = plen + xl + t0 + (uint32_t)ad0;
-                        hist_run(P, io, len0, cnt, (int32_t)len_step);
-                    }
-                } else if constexpr (MODE == FZM_EXISTS) {
-                    // each element's length is compared with the target; the
-                    // wave looks at the lanes' verdicts once per chunk
-                    int32_t ad = ad0;
-                    uint32_t len = plen + xl + t0 + (uint32_t)ad0;
-                    bool hit = false;
-                    for (;;) {
-                        const bool c0 = ad >= 0;
-                        if (!__ballot(c0)) break;
-                        const bool c1 = ad >= delta;
-                        cnt += c0 ? 1u : 0u;
-                        cnt += c1 ? 1u : 0u;
-                        hit = hit || (c0 && len == target) || (c1 && len + len_step == target);
-                        ad -= 2 * delta;
-                        len += 2 * len_step;
-                    }
-                    lane_el += cnt;
-                    if (__ballot(hit)) {
-                        __hip_atomic_store(io.found, 1u, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                        return true;
-                    }
-                } else { // FZM_STORE
-                    uint64_t L = 0;
-                    if (ad0 >= 0) L = fdiv((uint32_t)ad0, P.div_delta) + 1;
-                    const uint64_t incl = wave_incl_scan64(L, lane);
-                    const uint64_t T = readlane64(incl, FZK_WAVE - 1);
-                    io.s_incl[lane] = incl;
-                    io.s_t0[lane] = t0;
-                    io.s_ad0[lane] = (uint32_t)ad0;
-                    if (x_in_lds) io.s_x[lane] = xl;
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    // Rows are produced 64 at a time (lane = position in the
-                    // chunk's output), staged in LDS as one contiguous block
-                    // and written out as consecutive dwords: every store
-                    // instruction covers 256 bytes.
-                    const uint64_t lim = P.max_tuples;
-                    const uint32_t du = P.d_user;
-                    for (uint64_t p0 = 0; p0 < T && rank + p0 < lim; p0 += FZK_WAVE) {
-                        const uint64_t left = T - p0 < lim - rank - p0 ? T - p0 : lim - rank - p0;
-                        const uint32_t nb = left < FZK_WAVE ? (uint32_t)left : FZK_WAVE;
-                        const uint64_t p = p0 + lane;
-                        if (lane < nb) {
-                            uint32_t j = 0;
-#pragma unroll
-                            for (uint32_t st = FZK_WAVE / 2; st >= 1; st >>= 1)
-                                if (io.s_incl[j + st - 1] <= p) j += st;
-                            const uint32_t k = (uint32_t)(p - (j ? io.s_incl[j - 1] : 0ull));
-                            // coordinates a[0..M-1], x, t, ad; the first pad
-                            // (virtual) coordinates are not output
-                            uint32_t *st_row = io.s_stage + lane * du;
-#pragma unroll
-                            for (int q = 0; q < MAXM; ++q)
-                                if (q < (int)M && (uint32_t)q >= P.pad) st_row[q - P.pad] = a[q];
-                            if (M >= P.pad)
-                                st_row[M - P.pad] = x_in_lds ? io.s_x[j] : (uint32_t)xbase + j;
-                            if (M + 1 >= P.pad) st_row[M + 1 - P.pad] = io.s_t0[j] + k * P.ord;
-                            st_row[M + 2 - P.pad] = io.s_ad0[j] - k * P.delta;
-                        }
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                        uint32_t *dst = io.out + (rank + p0) * du;
-                        const uint32_t words = nb * du;
-                        for (uint32_t i = lane; i < words; i += FZK_WAVE) dst[i] = io.s_stage[i];
-                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                        __builtin_amdgcn_wave_barrier();
-                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                    if (rank < lim) n_el += (T < lim - rank) ? T : (lim - rank);
-                    rank += T;
-                    if (rank >= lim) return true;
-                }
-                return false;
-            };
             if constexpr (PAIR) {
                 // Only the lane prefixes with an element: the pair remainders
                 // v = Rp - x G2 (x in [xs, xlast]) that the last pair
@@ -947,7 +1092,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
     WalkOut o;
     o.elements = MODE == FZM_STORE ? n_el : wave_sum64(lane_el);
     o.rows = n_rows;
-    o.prefixes = wave_sum64(lane_pref);
+    o.prefixes = wave_sum64(lane_pref + lane_pref64);
     return o;
 }
 
@@ -963,7 +1108,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     constexpr uint32_t NP = M + 1;
     const uint32_t lane = __lane_id();
     const uint32_t wave = threadIdx.x / FZK_WAVE;
-    const uint32_t W = P.n_slices;
+    const uint32_t W = uni(Bf.ctl->slices); // cut by fz_slices_kernel
 
     // TLDS: the residue table is staged in LDS (read with ds_read); else it
     // is read from global memory.  Two instantiations keep each pointer's
@@ -1005,7 +1150,10 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     // The spine of this loop must stay free of lane-dependent branches: every
     // lane takes part in the cursor atomic (only lane 0 adds 1) and every lane
     // stores the same slice record, so the wave walks each slice as a whole.
-    for (;;) {
+    // (a wave whose index is past the slice count has nothing to take: it
+    // leaves without touching the cursor)
+    const bool idle = blockIdx.x * (FZK_WG / FZK_WAVE) + wave >= W;
+    for (; !idle;) {
         const uint32_t old = atomicAdd(&Bf.ctl->cursor, lane == 0 ? 1u : 0u);
         const uint32_t s = __builtin_amdgcn_readlane(old, 0);
         if (s >= W) break;
@@ -1074,7 +1222,8 @@ __global__ void fz_hist_reduce_kernel(const uint64_t *rows, uint32_t nwg, uint32
 __global__ void fz_slice_sums_kernel(FzPlan P, FzBufs Bf)
 {
     uint64_t el = 0, rows = 0, pref = 0, bad = 0;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < P.n_slices;
+    const uint32_t W = Bf.ctl->slices;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < W;
          s += gridDim.x * blockDim.x) {
         const FzSliceRec r = Bf.recs[s];
         el += r.elements;
