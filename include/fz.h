@@ -224,7 +224,9 @@ int fz_server_destroy(fz_server *s);
 /* Work statistics of the last successful enumeration on this device:
  * slices used, rows walked (one row = one prefix a_1..a_{d-3}), prefixes
  * (a_1..a_{d-2}) visited by lanes, candidate steps taken (one per element
- * visited plus one failing test per prefix), and elements. */
+ * visited plus one failing test per prefix), and elements.  After fz_batch
+ * the slices are the batch's work items, and the other figures are summed
+ * over them only while profiling is on (fz_profile_enable), else 0. */
 typedef struct {
     uint64_t slices;
     uint64_t rows;
@@ -270,7 +272,22 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * queries: a query whose whole modelled work is small is cut into fewer
  * slices, each carrying at least this much work, so that it occupies a few
  * wavefronts briefly; default 65536, about a thousand wavefront
- * instructions; 1: always the full slice count).  FZ_EINVAL for an
+ * instructions; 1: always the full slice count), "variant" (0: the plain
+ * walk; 1: count, histogram and predicate of a query with d >= 4 that is
+ * walked without row skipping or pair table also skip, by the common divisor
+ * of the last two and of the last three generators (Sec. 3.2.4), the lane
+ * prefixes and rows that cannot hold an element, and count a lane's run of
+ * elements in closed form), "tables" (count, histogram and predicate of a
+ * single query: 0: build the count and work tables unless they would take
+ * more than 64 GiB; 1: always; 2: never.  Without tables the slices are cut
+ * by splitWork (Sec. 4) from the set's lexicographic range, halving each
+ * range where its estimated number of elements is split in two),
+ * "host_threads" (hybrid pool, Sec. 6.3: count, histogram and predicate of
+ * a single query with tables: that many host threads, 0..64, walk the last
+ * slices of the work while the device walks the others; 0: off) and
+ * "host_share_ppm" (their share of the modelled work in millionths, up to
+ * 500000; 0: 3 per thread, about a host thread's rate against the device's).
+ * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */
 int fz_config_set(const char *key, int64_t value);

@@ -11,6 +11,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fz.h"
@@ -26,6 +27,13 @@ constexpr uint32_t kMaxSlices = 1u << 22;
 // Least modelled work of a single query's slice (1/64 wave instructions):
 // about a thousand wave instructions, a few microseconds.
 constexpr uint64_t kMinSliceWork = 1u << 16;
+// Count and work tables of a single order-free query above this size are not
+// built: its slices are cut by splitWork instead (the table-free walk).
+constexpr uint64_t kTableBudget = 64ull << 30;
+// Hybrid pool: a host thread walks about 1e7 elements per second against
+// ~3e12 on MI355X, so each thread takes about 3 millionths of the work.
+constexpr uint32_t kHostPpmPerThread = 3;
+constexpr uint32_t kMaxHostThreads = 64;
 constexpr size_t kLdsHistBudget = 64 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
 // per-wave LDS histogram in batches, 8 KB per wave: 1024 64-bit bins, or
@@ -58,6 +66,12 @@ struct Ctx {
     BatchSlot batch; // fz_batch
     bool last_batch = false; // fz_last_slices reads the batch's items
     fz_stats last{};
+    // hybrid pool: the host slices' bounds and base ranks (pinned), the
+    // event after their copy, the host part's histogram of the last call
+    void *h_hostb = nullptr;
+    size_t h_hostb_cap = 0;
+    hipEvent_t host_ev = nullptr;
+    std::vector<uint64_t> host_hist;
 };
 
 std::mutex g_mu;
@@ -72,9 +86,14 @@ uint32_t g_walk_order = 0; // 0: descending for order-free consumers, 1: the cal
 uint32_t g_batch_graph = 1; // batch phase 2 as a HIP graph (1) or plain launches (0)
 uint32_t g_pair_mode = 0;   // pair table: 0 by sparsity of the last pair, 1 always, 2 never
 uint64_t g_min_slice_work = 0; // 0: kMinSliceWork
+uint32_t g_variant = 0; // 1: the variant walk (common-divisor skip, closed-form run lengths)
+uint32_t g_tables = 0;  // 0: count tables unless above kTableBudget, 1: always, 2: never
+uint32_t g_host_threads = 0; // hybrid pool: host worker threads (0: off)
+uint32_t g_host_ppm = 0;     // their share of the work in millionths (0: kHostPpmPerThread each)
 
 bool worth_pruning(const FzPlan &P);
 bool worth_pair(const FzPlan &P);
+hipError_t ensure_pinned(void **p, size_t *cap, size_t bytes);
 uint64_t pair_words(const FzPlan &P);
 
 struct ProfEntry {
@@ -324,6 +343,37 @@ struct Launch {
     uint32_t nwg;
 };
 
+// The variant walk (knob "variant"): order-free consumers of a query walked
+// by the block walker (d >= 4, no row skipping, no pair table) skip, besides
+// the rows and lane prefixes of the plain walk, every lane coordinate x whose
+// remainder the last pair's common divisor D does not divide, and every row
+// of the deepest row level whose remainder D3 = gcd(G2, A, B) does not
+// divide (Sec. 3.2.4: a common divisor of the last generators), and count a
+// lane's run of elements in closed form.  Strides that would leave the
+// 31-bit remainders are not taken (the walk is then the same, only slower).
+void set_variant(FzPlan &P)
+{
+    P.cdv = 0;
+    if (g_variant != 1 || P.mode == FZM_STORE || P.prune || P.pair || P.d < 4) return;
+    const uint64_t D = P.D;
+    const uint64_t e2 = gcd64(P.G2, D);
+    uint64_t sx = D / e2;
+    if (sx >= (1u << 16) || (uint64_t)P.G2 * sx >= (1ull << 31)) sx = 1;
+    const uint64_t gy = P.g[P.d - 4];
+    const uint64_t D3 = e2;
+    const uint64_t e3 = gcd64(gy, D3);
+    uint64_t sy = D3 / e3;
+    if (sy >= (1u << 16) || gy * sy >= (1ull << 31)) sy = 1;
+    P.cd_sx = (uint32_t)sx;
+    P.cd_e2 = (uint32_t)e2;
+    P.cd_inv2 = sx > 1 ? modinv((P.G2 / e2) % sx, sx) : 0;
+    P.cd_D3 = (uint32_t)D3;
+    P.cd_sy = (uint32_t)sy;
+    P.cd_e3 = (uint32_t)e3;
+    P.cd_inv3 = sy > 1 ? modinv((gy / e3) % sy, sy) : 0;
+    P.cdv = 1;
+}
+
 // Slice count, walker grid and walker variant of plan P on a device with
 // `cus` compute units (no allocation).
 void plan_launch(int cus, FzPlan &P, Launch &L)
@@ -336,11 +386,30 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
     L.nwg = (uint32_t)std::min<uint64_t>((uint64_t)cus * wgcu,
                                          (P.n_slices + (FZK_WG / FZK_WAVE) - 1) / (FZK_WG / FZK_WAVE));
     P.hist_in_lds = (P.mode == FZM_HIST) &&
-                    ((size_t)P.nbins * 8 <= kLdsHistBudget); // one set per workgroup
+                    (((size_t)P.nbins + 1) * 8 <= kLdsHistBudget); // one set per workgroup
     P.prune = (g_prune_mode == 1 || (g_prune_mode == 0 && worth_pruning(P))) ? 1 : 0;
     P.pair = worth_pair(P) ? 1 : 0;
     if (P.pair && g_prune_mode != 2) P.prune = 1; // the pair walker skips empty rows too
     if (P.d < 4) P.prune = P.pair = 0;
+    // table-free walk: order-free consumers whose tables would pass the
+    // budget (or every one, knob "tables" = 2); stores place rows by rank
+    // and always have tables
+    const uint64_t table_bytes = (uint64_t)(2 * P.d - 3) * P.stride * 8;
+    P.notab = (P.mode != FZM_STORE &&
+               (g_tables == 2 || (g_tables == 0 && table_bytes > kTableBudget))) ? 1 : 0;
+    if (P.notab) {
+        P.prune = P.pair = 0;
+        P.min_slice_work = 0; // no work table: always the full slice count
+    }
+    // hybrid pool (order-free consumers with tables): host threads take the
+    // last slices of the work
+    P.host_slices = 0;
+    P.host_ppm = 0;
+    if (g_host_threads && !P.notab && P.mode != FZM_STORE) {
+        P.host_slices = g_host_threads;
+        P.host_ppm = g_host_ppm ? g_host_ppm : kHostPpmPerThread * g_host_threads;
+    }
+    set_variant(P);
 }
 
 // Bytes of each device buffer a single query of plan P needs.
@@ -351,16 +420,16 @@ struct ScratchSizes {
 ScratchSizes scratch_sizes(const FzPlan &P, const Launch &L)
 {
     ScratchSizes z;
-    z.S = (size_t)(P.d - 1) * P.stride * 8;
-    z.C = (size_t)(P.d - 2) * P.stride * 8;
+    z.S = P.notab ? 8 : (size_t)(P.d - 1) * P.stride * 8;
+    z.C = P.notab ? 8 : (size_t)(P.d - 2) * P.stride * 8;
     z.restab = (size_t)2 * P.B * sizeof(int2);
-    z.bounds = (size_t)(P.n_slices + 1) * (P.d - 2) * 4;
-    z.base = (size_t)(P.n_slices + 1) * 8;
+    z.bounds = (size_t)(P.n_slices + P.host_slices + 1) * (P.d - 2) * 4;
+    z.base = (size_t)(P.n_slices + P.host_slices + 1) * 8;
     z.recs = (size_t)P.n_slices * sizeof(FzSliceRec);
     z.ctl = sizeof(FzCtl);
     z.dpart = (size_t)FZK_DP_UNITS * 8;
     z.pt = P.pair ? (size_t)pair_words(P) * 8 : 0;
-    z.hist = P.mode == FZM_HIST ? (size_t)P.nbins * 8 : 0;
+    z.hist = P.mode == FZM_HIST ? ((size_t)P.nbins + 1) * 8 : 0; // and a spare bin
     z.hist_rows = (P.mode == FZM_HIST && P.hist_in_lds) ? (size_t)L.nwg * P.nbins * 8 : 0;
     return z;
 }
@@ -411,23 +480,130 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     return FZ_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Hybrid pool (Sec. 6.3): host threads walk the last few slices of a query
+// while the device walks the others.  A host worker walks its slice [b0, b1)
+// of prefixes (a_1 .. a_{d-2}) in ascending lexicographic order and, for each
+// prefix with remainder R, the elements of the last pair: the first a_{d-1}
+// with A a_{d-1} = R (mod B), then steps of (ord, -delta) while a_d >= 0
+// (the modulo skip of Sec. 3.2.4).  Counts, a plain length histogram, or the
+// length predicate.
+// ---------------------------------------------------------------------------
+struct HostPart {
+    uint64_t elements = 0;
+    bool found = false;
+    std::vector<uint64_t> hist;
+};
+
+void host_walk(const FzPlan &P, const uint32_t *b0, const uint32_t *b1, HostPart &o)
+{
+    const uint32_t K = P.d - 2;
+    if (P.mode == FZM_HIST) o.hist.assign(P.nbins, 0);
+    if (b0[0] == FZK_SENTINEL) return; // an empty slice
+    const bool open = b1[0] == FZK_SENTINEL;
+    uint32_t a[FZK_MAX_D];
+    uint64_t rr[FZK_MAX_D + 1];
+    rr[0] = P.n;
+    uint64_t plen = 0;
+    for (uint32_t k = 0; k < K; ++k) {
+        a[k] = b0[k];
+        rr[k + 1] = rr[k] - (uint64_t)a[k] * P.g[k];
+        plen += a[k];
+    }
+    const uint64_t A = P.A, Bg = P.B, D = P.D, ord = P.ord, dl = P.delta, inv = P.inv;
+    for (;;) {
+        if (!open) { // stop at the end bound
+            uint32_t k = 0;
+            while (k < K && a[k] == b1[k]) ++k;
+            if (k == K || a[k] > b1[k]) break;
+        }
+        const uint64_t R = rr[K];
+        if (R % D == 0) {
+            const uint64_t t0 = ((R / D) % ord) * inv % ord;
+            if (A * t0 <= R) {
+                uint64_t e = (R - A * t0) / Bg, t = t0;
+                for (;;) { // one element per step
+                    ++o.elements;
+                    const uint64_t len = plen + t + e;
+                    if (P.mode == FZM_HIST) ++o.hist[len];
+                    else if (P.mode == FZM_EXISTS && len == P.target_len) o.found = true;
+                    if (e < dl) break;
+                    e -= dl;
+                    t += ord;
+                }
+            }
+        }
+        // the next prefix: the deepest coordinate that can grow
+        int kk = (int)K - 1;
+        while (kk >= 0 && rr[kk + 1] < P.g[kk]) --kk;
+        if (kk < 0) break;
+        ++a[kk];
+        rr[kk + 1] -= P.g[kk];
+        for (uint32_t j = kk + 1; j < K; ++j) {
+            plen -= a[j];
+            a[j] = 0;
+            rr[j + 1] = rr[j];
+        }
+        plen += 1;
+    }
+}
+
 // Queues the whole path for one query and waits: count table, residue table,
 // slice bounds, walker, finalize, control-block readback.
 int run_query(Ctx &c, FzPlan &P, FzBufs &B, const Launch &L, hipStream_t s)
 {
-    FZ_LAUNCH("dp", s, fzk_launch_dp(P, B, s));
+    if (!P.notab) FZ_LAUNCH("dp", s, fzk_launch_dp(P, B, s));
     FZ_LAUNCH("restab", s, fzk_launch_restab(P, B, s));
-    FZ_LAUNCH("slices", s, fzk_launch_slices(P, B, s));
+    if (P.notab) FZ_LAUNCH("slices", s, fzk_launch_split(P, B, s));
+    else FZ_LAUNCH("slices", s, fzk_launch_slices(P, B, s));
+    // hybrid pool: the host slices' bounds and base ranks come back while
+    // the device walks its own
+    const uint32_t T = P.host_slices, W = P.n_slices, KP = P.d - 2;
+    uint32_t *hb = nullptr;
+    uint64_t *hbase = nullptr;
+    if (T) {
+        const size_t bb = (size_t)(T + 1) * KP * 4, bo = (bb + 7) & ~(size_t)7;
+        FZ_TRY(ensure_pinned(&c.h_hostb, &c.h_hostb_cap, bo + (size_t)(T + 1) * 8));
+        hb = (uint32_t *)c.h_hostb;
+        hbase = (uint64_t *)((char *)c.h_hostb + bo);
+        FZ_TRY(hipMemcpyAsync(hb, B.bounds + (uint64_t)W * KP, bb, hipMemcpyDeviceToHost, s));
+        FZ_TRY(hipMemcpyAsync(hbase, B.base + W, (size_t)(T + 1) * 8, hipMemcpyDeviceToHost, s));
+        if (!c.host_ev) FZ_TRY(hipEventCreateWithFlags(&c.host_ev, hipEventDisableTiming));
+        FZ_TRY(hipEventRecord(c.host_ev, s));
+    }
     static const char *const kEnumNames[] = {"enum.count", "enum.hist", "enum.exists",
                                              "enum.store"};
     FZ_LAUNCH(kEnumNames[P.mode & 3], s, fzk_launch_enum(P, B, L.nwg, s));
     FZ_LAUNCH("finalize", s, fzk_launch_finalize(P, B, L.nwg, s));
     FZ_TRY(hipMemcpyAsync(c.host_ctl, B.ctl, sizeof(FzCtl), hipMemcpyDeviceToHost, s));
+    std::vector<HostPart> parts(T);
+    if (T) {
+        FZ_TRY(hipEventSynchronize(c.host_ev));
+        std::vector<std::thread> th;
+        for (uint32_t t = 0; t < T; ++t)
+            th.emplace_back(host_walk, std::cref(P), hb + (size_t)t * KP, hb + (size_t)(t + 1) * KP,
+                            std::ref(parts[t]));
+        for (auto &x : th) x.join();
+    }
     FZ_TRY(hipStreamSynchronize(s));
     prof_collect();
-    const FzCtl &h = *c.host_ctl;
+    FzCtl &h = *c.host_ctl;
     if (h.status & FZS_OVERFLOW) return FZ_EOVERFLOW;
     if (h.status & FZS_MISMATCH) return FZ_EINTERNAL;
+    c.host_hist.clear();
+    if (T) { // fold the host part into the device's results
+        for (uint32_t t = 0; t < T; ++t) {
+            const HostPart &o = parts[t];
+            if (P.mode != FZM_EXISTS && o.elements != hbase[t + 1] - hbase[t]) return FZ_EINTERNAL;
+            h.count += o.elements;
+            h.found = h.found || o.found;
+            if (P.mode == FZM_HIST && o.hist.size() == P.nbins) {
+                if (c.host_hist.empty()) c.host_hist.assign(P.nbins, 0);
+                for (uint32_t l = 0; l < P.nbins; ++l) c.host_hist[l] += o.hist[l];
+            }
+        }
+    }
     c.last.slices = h.slices;
     c.last_batch = false;
     c.last.rows = h.rows;
@@ -1005,6 +1181,20 @@ int do_batch(const fz_query *qs, fz_result *rs, uint32_t nq, void *stream)
     for (uint32_t i = 0; i < nq; ++i) batch_result(c.batch, qs[i], i, &rs[i]);
     c.last.slices = c.batch.n_items;
     c.last_batch = true;
+    c.last.rows = c.last.prefixes = c.last.elements = c.last.candidates = 0;
+    if (g_prof && c.batch.n_items) {
+        // walker statistics of the batch (profiling runs only: a readback
+        // of every item's record)
+        std::vector<FzSliceRec> recs(c.batch.n_items);
+        FZ_TRY(hipMemcpy(recs.data(), c.batch.recs.p, recs.size() * sizeof(FzSliceRec),
+                         hipMemcpyDeviceToHost));
+        for (const FzSliceRec &r : recs) {
+            c.last.rows += r.rows;
+            c.last.prefixes += r.prefixes;
+            c.last.elements += r.elements;
+        }
+        c.last.candidates = c.last.elements + c.last.prefixes;
+    }
     return FZ_OK;
 }
 
@@ -1065,6 +1255,7 @@ int do_count_noalloc(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
     if ((rc = noalloc_device(&a))) return rc;
     Launch L;
     plan_launch(a->cus, P, L);
+    P.host_slices = P.host_ppm = 0; // the device walks every slice here
     const ScratchSizes z = scratch_sizes(P, L);
     // 256-byte aligned pieces of the array, in a fixed order
     size_t off = 0;
@@ -1093,9 +1284,9 @@ int do_count_noalloc(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
     }
     bind_pair(P, pt, B);
     const hipStream_t s = (hipStream_t)stream;
-    FZ_TRY(fzk_launch_dp(P, B, s));
+    if (!P.notab) FZ_TRY(fzk_launch_dp(P, B, s));
     FZ_TRY(fzk_launch_restab(P, B, s));
-    FZ_TRY(fzk_launch_slices(P, B, s));
+    FZ_TRY(P.notab ? fzk_launch_split(P, B, s) : fzk_launch_slices(P, B, s));
     FZ_TRY(fzk_launch_enum(P, B, L.nwg, s));
     FZ_TRY(fzk_launch_finalize(P, B, L.nwg, s));
     FzCtl h;
@@ -1162,13 +1353,24 @@ int fz_length_hist(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *bins, ui
     if (h.count != h.total) return FZ_EINTERNAL;
     std::vector<uint64_t> tmp(P.nbins);
     FZ_TRY(hipMemcpy(tmp.data(), B.hist, (size_t)P.nbins * 8, hipMemcpyDeviceToHost));
+    uint64_t lo = h.min_len, hi = h.max_len;
+    if (!c->host_hist.empty()) { // the hybrid pool's host part
+        for (uint32_t l = 0; l < P.nbins; ++l) tmp[l] += c->host_hist[l];
+        lo = UINT64_MAX;
+        hi = 0;
+        for (uint32_t l = 0; l < P.nbins; ++l)
+            if (tmp[l]) {
+                lo = std::min<uint64_t>(lo, l);
+                hi = l;
+            }
+    }
     uint64_t sum = 0;
     for (uint64_t v : tmp) sum += v;
     if (sum != h.count) return FZ_EINTERNAL;
     std::memcpy(bins, tmp.data(), (size_t)P.nbins * 8);
     for (uint64_t l = P.nbins; l < nbins; ++l) bins[l] = 0;
-    *min_len = h.count ? h.min_len : UINT64_MAX;
-    *max_len = h.count ? h.max_len : 0;
+    *min_len = h.count ? lo : UINT64_MAX;
+    *max_len = h.count ? hi : 0;
     return FZ_OK;
 }
 
@@ -1298,6 +1500,11 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "batch_graph") == 0 && value <= 1) g_batch_graph = (uint32_t)value;
     else if (std::strcmp(key, "pair_table") == 0 && value <= 2) g_pair_mode = (uint32_t)value;
     else if (std::strcmp(key, "min_slice_work") == 0) g_min_slice_work = (uint64_t)value;
+    else if (std::strcmp(key, "variant") == 0 && value <= 1) g_variant = (uint32_t)value;
+    else if (std::strcmp(key, "tables") == 0 && value <= 2) g_tables = (uint32_t)value;
+    else if (std::strcmp(key, "host_threads") == 0 && value <= kMaxHostThreads)
+        g_host_threads = (uint32_t)value;
+    else if (std::strcmp(key, "host_share_ppm") == 0 && value <= 500000) g_host_ppm = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

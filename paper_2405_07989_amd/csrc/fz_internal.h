@@ -60,6 +60,26 @@ struct FzPlan {
     uint64_t target_len; // predicate target
     uint64_t max_tuples; // store limit; UINT64_MAX for the other consumers
     uint64_t min_slice_work; // single query: least modelled work of a slice (0: always W)
+    // The variant walk (cdv = 1): the common-divisor skip of the last two and
+    // three generators (Sec. 3.2.4) and closed-form run lengths.  A lane
+    // coordinate x can have an element only when x G2 = R (mod D), D =
+    // gcd(A, B): e2 = gcd(G2, D) must divide R, and then x = ((R mod D) / e2)
+    // inv2 (mod sx), sx = D / e2.  Likewise the rows of the deepest row level
+    // with D3 = gcd(G2, A, B) = e2: e3 = gcd(g[d-4], D3), sy = D3 / e3.
+    uint32_t cdv;
+    uint32_t cd_sx, cd_e2, cd_inv2;
+    uint32_t cd_D3, cd_sy, cd_e3, cd_inv3;
+    // Table-free walk (notab = 1; count, histogram and predicate only): no
+    // count or work table; the W slices are cut by repeated splitWork
+    // (Sec. 4, Alg. 4.1) from the whole set, and no slice is checked
+    // against ranks.
+    uint32_t notab;
+    // Hybrid pool (host_slices = T > 0; count, histogram and predicate of a
+    // single query with tables): slices W..W+T-1 cover the last host_ppm
+    // millionths of the modelled work and are walked by T host threads while
+    // the device walks slices 0..W-1 (n_slices = W).
+    uint32_t host_slices;
+    uint32_t host_ppm;
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag
@@ -173,6 +193,7 @@ struct FzBatchBufs {
 hipError_t fzk_launch_dp(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_restab(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_slices(const FzPlan &p, const FzBufs &b, hipStream_t s);
+hipError_t fzk_launch_split(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_enum(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s);
 hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s);
 hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *ranks,

@@ -430,7 +430,19 @@ __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64
         const uint32_t x = unrank_level(SM, v, P.G2, r);
         Wtot = acc + row_work(P, SM, v, x + 1, PC);
     }
-    uint64_t rc = (Wtot / W) * j + ((Wtot % W) * j) / W;
+    // work rank of bound j: W equal parts, or, with a host share, W - T
+    // equal parts of the device's work and T of the host's
+    uint64_t rc;
+    const uint32_t T = P.host_slices;
+    if (T == 0) {
+        rc = (Wtot / W) * j + ((Wtot % W) * j) / W;
+    } else {
+        const uint32_t Wd = W - T;
+        const uint64_t Wh = (uint64_t)((double)Wtot * (P.host_ppm * 1e-6));
+        const uint64_t Wdev = Wtot - Wh;
+        rc = j <= Wd ? (Wdev / Wd) * j + ((Wdev % Wd) * j) / Wd
+                     : Wdev + (Wh / T) * (j - Wd) + ((Wh % T) * (j - Wd)) / T;
+    }
     uint64_t base = 0;
     uint32_t v = P.n;
     for (uint32_t k = 0; k < M; ++k) {
@@ -458,7 +470,7 @@ __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64
 // of every wave of the chip).  Every thread computes the same value.
 __device__ __forceinline__ uint32_t cut_slices(const FzPlan &P, const uint64_t *C)
 {
-    if (P.min_slice_work == 0) return P.n_slices;
+    if (P.min_slice_work == 0 || P.host_slices) return P.n_slices;
     const uint64_t k = C[P.n] / P.min_slice_work + 1;
     return k < P.n_slices ? (uint32_t)k : P.n_slices;
 }
@@ -481,11 +493,12 @@ __global__ void fz_slices_kernel(FzPlan P, FzBufs Bf)
         c->prefixes = 0;
         c->written = 0;
     }
-    if (j > W) return;
+    const uint32_t Wall = W + P.host_slices; // and the host's slices after the device's
+    if (j > Wall) return;
     // a predicate's walkers may stop before taking every slice: slices
     // nobody walks must read as empty in the totals
     if (j < W) Bf.recs[j] = FzSliceRec{};
-    Bf.base[j] = slice_bound(P, Bf.S, Bf.C, W, j, Bf.bounds + (uint64_t)j * (P.d - 2), Bf.PC);
+    Bf.base[j] = slice_bound(P, Bf.S, Bf.C, Wall, j, Bf.bounds + (uint64_t)j * (P.d - 2), Bf.PC);
 }
 
 // ---------------------------------------------------------------------------
@@ -530,9 +543,29 @@ struct WalkOut {
 // are two's complement: 64-bit bins, or 32-bit ones in a batch, where a bin
 // moves by at most the elements of one work item (< 2^30, checked on the
 // host) and is flushed, sign-extended, after every item.
+template <bool FIXED>
 __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint32_t len0,
                                          uint32_t cnt, int32_t step)
 {
+    if constexpr (FIXED) {
+        // A single query's bins (LDS or global, 64-bit) have one spare bin
+        // at index nbins that takes the -1 of a run ending past the last bin
+        // (and of every run when step is 0), so both adds are unconditional.
+        const uint32_t mag = step < 0 ? (uint32_t)-step : (uint32_t)step;
+        const uint32_t lo = step < 0 ? len0 - (cnt - 1) * mag : len0;
+        const uint32_t hi0 = lo + cnt * mag;
+        const uint32_t hi = (mag != 0 && hi0 < P.nbins) ? hi0 : P.nbins;
+        const uint64_t inc = mag != 0 ? 1ull : (uint64_t)cnt;
+        if (P.hist_in_lds) { // the workgroup's bins
+            __hip_atomic_fetch_add(&io.wbins[lo], inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&io.wbins[hi], ~0ull, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            __hip_atomic_fetch_add(&io.gbins[lo], inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&io.gbins[hi], ~0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
     uint32_t lo = len0, inc = cnt;
     uint64_t hi = ~0ull;
     if (step != 0) {
@@ -657,21 +690,27 @@ __device__ __forceinline__ void count_steps(uint32_t &cnt, int32_t &ad, int32_t 
 
 // FIXED: M == MAXM (a compile-time depth: the single-query walker), which
 // allows the row fast paths below without per-level selects.
-template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED>
+// CDV: the variant walk of the block walker (common-divisor skip over the
+// last two and three generators, Sec. 3.2.4, and each lane's run counted in
+// closed form): neighbouring lanes are sx apart in x and block rows sy apart.
+template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED, bool CDV = false>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                                               const uint32_t *b0, const uint32_t *b1,
                                               uint64_t rank, const WalkIO &io, uint32_t lane)
 {
-    // lane * G2 = lq * B + lr (exact whenever the lane is active).  A lane
-    // reads the doubled residue table at rho' = Pc + (B - lr) with quotient
-    // q' = Qc - (lq + 1): no borrow to propagate.
-    const uint64_t lg = (uint64_t)lane * P.G2;
+    // The lanes of a chunk are G2s = G2 sx apart in remainder (sx = 1 but in
+    // the variant walk).  lane * G2s = lq * B + lr (exact whenever the lane
+    // is active).  A lane reads the doubled residue table at rho' = Pc + (B -
+    // lr) with quotient q' = Qc - (lq + 1): no borrow to propagate.
+    const uint32_t sx = CDV ? P.cd_sx : 1u;
+    const uint32_t G2s = P.G2 * sx; // < 2^31 (checked on the host)
+    const uint64_t lg = (uint64_t)lane * G2s;
     const uint32_t lq1 = (uint32_t)(lg / P.B) + 1;
     const uint32_t lr2 = P.B - (uint32_t)(lg % P.B);
-    // 64 G2 = c64q B + c64r: the step of a chunk's remainder (c64q wraps
+    // 64 G2s = c64q B + c64r: the step of a chunk's remainder (c64q wraps
     // only when no second chunk fits in a row, and is then unused)
-    const uint32_t g2q = fdiv(P.G2, P.div_B);
-    const uint32_t g2r64 = (P.G2 - g2q * P.B) * FZK_WAVE; // < 64 B <= 2^30
+    const uint32_t g2q = fdiv(G2s, P.div_B);
+    const uint32_t g2r64 = (G2s - g2q * P.B) * FZK_WAVE; // < 64 B <= 2^30
     const uint32_t c64r0q = fdiv(g2r64, P.div_B);
     const uint32_t c64q = g2q * FZK_WAVE + c64r0q;
     const uint32_t c64r = g2r64 - c64r0q * P.B;
@@ -741,7 +780,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 // Dense walks enter the loop at once (almost every chunk has
                 // an element); the others test first.
                 int32_t ad = ad0;
-                if constexpr (BLOCKS) {
+                if constexpr (CDV) { // the run's length in closed form
+                    cnt = ad0 >= 0 ? fdiv((uint32_t)ad0, P.div_delta) + 1u : 0u;
+                } else if constexpr (BLOCKS) {
                     count_steps(cnt, ad, delta, delta2);
                 } else if (__ballot(ad >= 0)) {
                     do {
@@ -757,7 +798,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 // run is then recorded as a strided difference (finalize
                 // integrates along the stride).
                 int32_t ad = ad0;
-                if constexpr (BLOCKS) {
+                if constexpr (CDV) { // the run's length in closed form
+                    cnt = ad0 >= 0 ? fdiv((uint32_t)ad0, P.div_delta) + 1u : 0u;
+                } else if constexpr (BLOCKS) {
                     count_steps(cnt, ad, delta, delta2);
                 } else if (__ballot(ad >= 0)) {
                     do {
@@ -769,7 +812,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 lane_el += cnt;
                 if (cnt) {
                     const uint32_t len0 = plen + xl + t0 + (uint32_t)ad0;
-                    hist_run(P, io, len0, cnt, (int32_t)len_step);
+                    hist_run<FIXED>(P, io, len0, cnt, (int32_t)len_step);
                 }
             } else if constexpr (MODE == FZM_EXISTS) {
                 // each element's length is compared with the target; the
@@ -863,23 +906,86 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
         // lr2): the chunk loop is vector work but for its one branch.
         if constexpr (BLOCKS) {
             const uint32_t gy = P.g[MAXM > 0 ? MAXM - 1 : 0];
+            const uint32_t sy = CDV ? P.cd_sy : 1u;
+            // the chunk step of the table offsets, and 8 B kept in a vector
+            // register (it is added under a per-lane condition every chunk)
+            const uint32_t c64r8 = c64r * 8u, lr2_8 = lr2 * 8u;
+            uint32_t vB8 = P.B * 8u;
+            asm volatile("" : "+v"(vB8));
             for (;;) {
-                // rows y = a[M-1] + lane while in the set and in the slice
-                const uint32_t ay = a[MAXM - 1];
-                const uint32_t R0 = rr[MAXM];
-                const uint64_t off = (uint64_t)lane * gy;
+                uint32_t ay = a[MAXM - 1];
+                uint32_t R0 = rr[MAXM];
+                if constexpr (CDV) {
+                    // the first row at or after ay whose remainder is a
+                    // multiple of D3: y = ay + dy with dy (gy / e3) = (R0 mod
+                    // D3) / e3 (mod sy); none when e3 does not divide R0
+                    const uint32_t r3 = R0 % P.cd_D3;
+                    bool any = r3 % P.cd_e3 == 0;
+                    const uint32_t dy =
+                        any ? (uint32_t)((uint64_t)(r3 / P.cd_e3) * P.cd_inv3 % sy) : 0u;
+                    any = any && (uint64_t)dy * gy <= R0 && (!upper_eq || ay + dy <= e[MAXM - 1]);
+                    if (!any) {
+                        // nothing left on this level: the slice's end when its
+                        // end prefix is here, else the next prefix above
+                        if (upper_eq) break;
+                        int kk = -1;
+#pragma unroll
+                        for (int k = 0; k + 1 < MAXM; ++k)
+                            if (rr[k + 1] >= P.g[k]) kk = k;
+                        if (kk < 0) break;
+#pragma unroll
+                        for (int k = 0; k < MAXM; ++k) {
+                            if (k == kk) {
+                                a[k] += 1;
+                                rr[k + 1] -= P.g[k];
+                            } else if (k > kk) {
+                                a[k] = 0;
+                                rr[k + 1] = rr[k];
+                            }
+                        }
+                        plen = 0;
+#pragma unroll
+                        for (int k = 0; k < MAXM; ++k) plen += a[k];
+                        upper_eq = upper_equal();
+                        xs = 0;
+                        continue;
+                    }
+                    if (dy) xs = 0; // the slice's start row had no element
+                    ay += dy;
+                    R0 -= dy * gy;
+                    plen += dy;
+                    a[MAXM - 1] = ay;
+                    rr[MAXM] = R0;
+                }
+                // rows y = ay + lane sy while in the set and in the slice
+                const uint64_t off = (uint64_t)lane * sy * gy;
                 bool in = off <= R0;
-                if (upper_eq) in = in && ay + lane <= e[MAXM - 1];
+                if (upper_eq) in = in && ay + lane * sy <= e[MAXM - 1];
                 const uint32_t nb = (uint32_t)__builtin_popcountll(__ballot(in));
-                const bool blast = upper_eq && ay + nb - 1 == e[MAXM - 1];
+                // the slice's end row is the block's last row; no row of the
+                // slice is left after the block
+                const bool end_here = upper_eq && ay + (nb - 1) * sy == e[MAXM - 1];
+                const bool blast = upper_eq && ay + nb * sy > e[MAXM - 1];
                 const uint32_t R = R0 - (uint32_t)off; // meaningful for lanes in
-                const uint32_t x0 = lane == 0 ? (uint32_t)xs : 0u;
+                uint32_t x0 = lane == 0 ? (uint32_t)xs : 0u;
+                bool has = in;
+                if constexpr (CDV) {
+                    // the row's first x at or after x0 with x G2 = R (mod D)
+                    const uint32_t r2 = R % P.D;
+                    has = has && r2 % P.cd_e2 == 0;
+                    const uint32_t xst = (uint32_t)((uint64_t)(r2 / P.cd_e2) * P.cd_inv2 % sx);
+                    x0 += (xst + sx - x0 % sx) % sx;
+                }
                 const int32_t xlast =
-                    (blast && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
-                // the row's lane prefixes x0..xlast (rows of a stopped walk
-                // count in full)
-                const int32_t v_np = in && xlast >= (int32_t)x0 ? xlast - (int32_t)x0 + 1 : 0;
+                    (end_here && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
+                // the row's lane prefixes x0, x0 + sx, .., up to xlast (rows of
+                // a stopped walk count in full)
+                const int32_t v_np = has && xlast >= (int32_t)x0
+                                         ? (CDV ? (xlast - (int32_t)x0) / (int32_t)sx
+                                                : xlast - (int32_t)x0) + 1
+                                         : 0;
                 lane_pref64 += (uint32_t)v_np;
+                const uint32_t v_x0 = x0;
                 const uint32_t v_Rc = R - x0 * P.G2;
                 const uint32_t v_Qc = fdiv(v_Rc, P.div_B);
                 const uint32_t v_Pc = v_Rc - v_Qc * P.B;
@@ -890,9 +996,12 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     const uint32_t Qc = __builtin_amdgcn_readlane(v_Qc, j);
                     const uint32_t Pc = __builtin_amdgcn_readlane(v_Pc, j);
                     // the count does not look at x
-                    const int32_t xf = MODE == FZM_COUNT ? 0 : (j == 0 ? xs : 0);
-                    a[MAXM - 1] = ay + j;
-                    plen = plen0 + j;
+                    const int32_t xf =
+                        MODE == FZM_COUNT ? 0
+                                          : (CDV ? (int32_t)__builtin_amdgcn_readlane(v_x0, j)
+                                                 : (j == 0 ? xs : 0));
+                    a[MAXM - 1] = ay + j * sy;
+                    plen = plen0 + j * sy;
                     if constexpr (MODE == FZM_EXISTS) {
                         const uint32_t f = __hip_atomic_load(io.found, __ATOMIC_RELAXED,
                                                               __HIP_MEMORY_SCOPE_AGENT);
@@ -901,39 +1010,52 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                             break;
                         }
                     }
-                    uint32_t rho = Pc + lr2;          // in [lr2, lr2 + B), inside the 2B table
+                    // the lane's table entry as a byte offset: rho * 8, rho in
+                    // [lr2, lr2 + B), inside the 2B table
+                    uint32_t off = (Pc + lr2) * 8u;
                     int32_t q = (int32_t)(Qc - lq1);
                     int32_t c = xf;
-                    for (int32_t left = np - 1; left >= 0; left -= FZK_WAVE, c += FZK_WAVE) {
-                        const bool active = (int32_t)lane <= left;
-                        const int2 ent = TLDS ? io.ltab[rho] : io.gtab[rho];
-                        int32_t ad0 = q - ent.y;
-                        ad0 = (active && ad0 >= 0) ? ad0 : -1;
-                        if (consume((uint32_t)c + lane, (uint32_t)ent.x, ad0, c, false)) {
+                    int32_t left = np - 1;
+                    // Full chunks: every lane has an x.  An active lane's
+                    // first candidate is above -delta - 1, so its run needs
+                    // no clamp; the last chunk's lanes past the row's end get
+                    // -1 (their quotient is meaningless).
+                    for (; left >= FZK_WAVE - 1; left -= FZK_WAVE, c += FZK_WAVE * (int32_t)sx) {
+                        const int2 ent = TLDS ? *(const int2 *)((const char *)io.ltab + off)
+                                              : *(const int2 *)((const char *)io.gtab + off);
+                        if (consume((uint32_t)c + lane * sx, (uint32_t)ent.x, q - ent.y, c, false)) {
                             done = true;
                             break;
                         }
-                        rho -= c64r;
+                        off -= c64r8;
                         q -= (int32_t)c64q;
-                        if ((int32_t)rho < (int32_t)lr2) {
-                            rho += P.B;
+                        if ((int32_t)off < (int32_t)lr2_8) {
+                            off += vB8;
                             q -= 1;
                         }
+                    }
+                    if (!done && left >= 0) {
+                        const bool active = (int32_t)lane <= left;
+                        const int2 ent = TLDS ? *(const int2 *)((const char *)io.ltab + off)
+                                              : *(const int2 *)((const char *)io.gtab + off);
+                        int32_t ad0 = q - ent.y;
+                        ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                        done = consume((uint32_t)c + lane * sx, (uint32_t)ent.x, ad0, c, false);
                     }
                     if (done) break;
                 }
                 n_rows += j < nb ? j + 1 : nb;
                 if (done || blast) break;
                 // the block's last row, then the next row of the deepest
-                // level, else of a shallower one
-                a[MAXM - 1] = ay + nb - 1;
-                rr[MAXM] = R0 - (nb - 1) * gy;
-                plen = plen0 + nb - 1;
+                // level (sy further), else of a shallower one
+                a[MAXM - 1] = ay + (nb - 1) * sy;
+                rr[MAXM] = R0 - (nb - 1) * sy * gy;
+                plen = plen0 + (nb - 1) * sy;
                 xs = 0;
-                if (rr[MAXM] >= gy) {
-                    a[MAXM - 1] += 1;
-                    rr[MAXM] -= gy;
-                    plen += 1;
+                if ((uint64_t)rr[MAXM] >= (uint64_t)sy * gy) {
+                    a[MAXM - 1] += sy;
+                    rr[MAXM] -= sy * gy;
+                    plen += sy;
                     continue;
                 }
                 int kk = -1;
@@ -1134,7 +1256,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) { // one set of bins for the workgroup's waves
             io.wbins = (uint64_t *)scratch;
-            for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) io.wbins[i] = 0;
+            for (uint32_t i = threadIdx.x; i <= P.nbins; i += blockDim.x) io.wbins[i] = 0;
         }
     }
     // store scratch per wave: scan (64 x u64), t0, ad0 and x (64 x u32
@@ -1165,7 +1287,8 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
         const WalkOut o =
-            walk_slice<M, MODE, TLDS, (VAR >= 1), (VAR == 2), true>(P, M, b0, b0 + NP, Bf.base[s], io, lane);
+            walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2), (VAR == 2), true, (VAR == 3)>(
+                P, M, b0, b0 + NP, Bf.base[s], io, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -1229,7 +1352,8 @@ __global__ void fz_slice_sums_kernel(FzPlan P, FzBufs Bf)
         el += r.elements;
         rows += r.rows;
         pref += r.prefixes;
-        if (P.mode != FZM_EXISTS && r.elements != Bf.base[s + 1] - Bf.base[s]) bad = 1;
+        if (P.mode != FZM_EXISTS && !P.notab && r.elements != Bf.base[s + 1] - Bf.base[s])
+            bad = 1;
     }
     for (int o = FZK_WAVE / 2; o > 0; o >>= 1) {
         el += __shfl_xor(el, o);
@@ -1280,9 +1404,125 @@ __global__ void __launch_bounds__(1024) fz_finalize_kernel(FzPlan P, FzBufs Bf)
         FzCtl *c = Bf.ctl;
         c->min_len = L;
         c->max_len = H;
+        if (P.notab) c->total = c->count; // no count table: the walk's count
         const uint64_t N = c->total;
         c->written = (c->status & FZS_OVERFLOW) ? 0 : (N < P.max_tuples ? N : P.max_tuples);
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// splitWork without tables (Sec. 4, Alg. 4.1, and Remark 4.2's check).  A
+// slice is the half-open lexicographic range [a, b) of prefixes (a_1 ..
+// a_{d-2}); b may be the end of the set.  The new bound c keeps the prefix
+// a_1 .. a_{j-1} at the first level j where a and b differ and splits there
+// (Alg. 4.1 splits at that leftmost level; here the value of c_j is not
+// a_j - 1 but the one that halves the range's estimated number of elements,
+// from the leading term of |Z(R)|, so that repeated halving gives slices of
+// similar size), with zeros below.  If no value lies strictly between a_j
+// and b_j, c is b's prefix down to level j with zeros below when that is
+// still below b, else the split is made inside a's own subtree one level
+// deeper, and so on.  Returns false when no c lies strictly inside (a, b)
+// (Remark 4.2: the slice is then not split; its second half is empty).
+// Ascending walk: a worker keeps [a, c), the new one takes [c, b).
+// ---------------------------------------------------------------------------
+// Value t in (lo, hi) at level j (generator gj, remainder R before it, k
+// coordinates after it) with about as many elements in [lo, t) as in [t, hi):
+// the completions of values >= t number about (R - t gj)^k / const.
+__device__ uint32_t split_value(uint32_t lo, uint32_t hi, uint32_t R, uint32_t gj, uint32_t k)
+{
+    const double vlo = pow((double)R - (double)lo * gj, (double)k);
+    const double rhi = (double)hi * gj > (double)R ? 0.0 : (double)R - (double)hi * gj;
+    const double vhi = pow(rhi, (double)k);
+    const double mid = pow(0.5 * (vlo + vhi), 1.0 / k);
+    double t = ceil(((double)R - mid) / gj);
+    if (!(t > (double)lo)) t = (double)lo + 1;       // (also catches NaN)
+    if (t > (double)hi - 1) t = (double)hi - 1;
+    return (uint32_t)t;
+}
+
+__device__ bool split_bound(const FzPlan &P, const uint32_t *a, const uint32_t *b, uint32_t *c)
+{
+    const uint32_t K = P.d - 2;
+    if (a[0] == FZK_SENTINEL) return false; // [end, end): an empty slice
+    const bool b_end = b[0] == FZK_SENTINEL;
+    uint32_t j = 0, R = P.n;
+    if (!b_end)
+        while (j < K && a[j] == b[j]) {
+            R -= a[j] * P.g[j];
+            ++j;
+        }
+    if (j == K) return false; // a == b: an empty slice
+    // at level j: a_j < b_j (or b is the end: every value up to R / g_j)
+    const uint32_t hi = b_end ? R / P.g[j] + 1 : b[j];
+    for (uint32_t i = 0; i < K; ++i) c[i] = i < j ? a[i] : 0u;
+    if (hi - a[j] >= 2) {
+        c[j] = split_value(a[j], hi, R, P.g[j], P.d - 1 - j);
+        return true;
+    }
+    if (!b_end) {
+        bool deeper = false;
+        for (uint32_t i = j + 1; i < K; ++i) deeper = deeper || b[i] != 0;
+        if (deeper) { // (prefix, b_j, 0, ..) lies strictly between a and b
+            c[j] = b[j];
+            return true;
+        }
+    }
+    // inside a's subtree: the first deeper level with room above a's value
+    c[j] = a[j];
+    R -= a[j] * P.g[j];
+    for (uint32_t i = j + 1; i < K; ++i) {
+        const uint32_t hv = R / P.g[i] + 1;
+        if (hv - a[i] >= 2) {
+            c[i] = split_value(a[i], hv, R, P.g[i], P.d - 1 - i);
+            return true;
+        }
+        c[i] = a[i];
+        R -= a[i] * P.g[i];
+    }
+    return false;
+}
+
+// Bound 0 is the first prefix (0, .., 0), bound W the end of the set; the
+// control block starts as the slice kernel leaves it.
+__global__ void fz_split_init_kernel(FzPlan P, FzBufs Bf)
+{
+    const uint32_t K = P.d - 2;
+    for (uint32_t i = threadIdx.x; i < K; i += blockDim.x) {
+        Bf.bounds[i] = 0;
+        Bf.bounds[(uint64_t)P.n_slices * K + i] = i == 0 ? FZK_SENTINEL : 0u;
+    }
+    if (threadIdx.x == 0) {
+        FzCtl *c = Bf.ctl;
+        c->cursor = 0;
+        c->found = 0;
+        c->status = 0;
+        c->slices = P.n_slices;
+        c->total = 0;
+        c->count = 0;
+        c->rows = 0;
+        c->prefixes = 0;
+        c->written = 0;
+    }
+}
+
+__global__ void fz_split_round_kernel(FzPlan P, FzBufs Bf, uint32_t r)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (1u << r)) return;
+    uint32_t lo = 0, hi = P.n_slices;
+    for (uint32_t bit = r; bit-- > 0;) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if ((k >> bit) & 1u) lo = mid;
+        else hi = mid;
+    }
+    // every slice of the range is empty of records until walked
+    if (hi - lo < 2) return;
+    const uint32_t mid = lo + (hi - lo) / 2;
+    const uint32_t K = P.d - 2;
+    uint32_t *c = Bf.bounds + (uint64_t)mid * K;
+    if (!split_bound(P, Bf.bounds + (uint64_t)lo * K, Bf.bounds + (uint64_t)hi * K, c))
+        for (uint32_t i = 0; i < K; ++i) c[i] = Bf.bounds[(uint64_t)hi * K + i]; // empty
 }
 
 // ---------------------------------------------------------------------------
@@ -1663,12 +1903,36 @@ hipError_t fzk_launch_restab(const FzPlan &p, const FzBufs &b, hipStream_t s)
     return hipGetLastError();
 }
 
+// Table-free slices: W slices cut from the whole set by repeated
+// splitWork (Sec. 4): slice [0, W) is halved, then each half, and so on; a
+// thread of round r finds its index range by following the bits of its
+// index down from [0, W) and writes the bound in the middle of it, split
+// from the bounds at the range's ends.  Rounds run until every range holds
+// one slice.
+hipError_t fzk_launch_split(const FzPlan &p, const FzBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(fz_split_init_kernel, dim3(1), dim3(64), 0, s, p, b);
+    // slices no wave takes (a predicate that stopped) read as empty
+    hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, (uint64_t *)b.recs,
+                       (uint64_t)p.n_slices * (sizeof(FzSliceRec) / 8));
+    for (uint32_t r = 0; (1ull << r) < p.n_slices; ++r) {
+        const uint32_t ranges = 1u << r;
+        hipLaunchKernelGGL(fz_split_round_kernel, dim3((ranges + 255) / 256), dim3(256), 0, s, p, b,
+                           r);
+    }
+    if (p.mode == FZM_HIST)
+        hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.hist,
+                           (uint64_t)p.nbins + 1); // and the spare bin
+    return hipGetLastError();
+}
+
 hipError_t fzk_launch_slices(const FzPlan &p, const FzBufs &b, hipStream_t s)
 {
-    const uint32_t blocks = (p.n_slices + 1 + 255) / 256;
+    const uint32_t blocks = (p.n_slices + p.host_slices + 1 + 255) / 256;
     hipLaunchKernelGGL(fz_slices_kernel, dim3(blocks), dim3(256), 0, s, p, b);
     if (p.mode == FZM_HIST)
-        hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.hist, (uint64_t)p.nbins);
+        hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.hist,
+                           (uint64_t)p.nbins + 1); // and the spare bin
     return hipGetLastError();
 }
 
@@ -1676,7 +1940,7 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
 {
     const uint32_t waves = FZK_WG / FZK_WAVE;
     size_t bytes = p.restab_in_lds ? (size_t)2 * ((2 * p.B + 1) & ~1u) * sizeof(uint32_t) : 0;
-    if (p.mode == FZM_HIST && p.hist_in_lds) bytes += (size_t)p.nbins * sizeof(uint64_t);
+    if (p.mode == FZM_HIST && p.hist_in_lds) bytes += ((size_t)p.nbins + 1) * sizeof(uint64_t);
     if (p.mode == FZM_STORE)
         bytes += (size_t)waves * (5 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
     return bytes;
@@ -1700,8 +1964,9 @@ static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipSt
                            s, p, b);
         break;
     default:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
-                           s, p, b);
+        // (the variant walk counts runs in closed form: no store)
+        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS, VAR == 3 ? 0 : VAR>), dim3(nwg),
+                           dim3(FZK_WG), lds, s, p, b);
         break;
     }
 }
@@ -1711,8 +1976,11 @@ static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipSt
 template <int M>
 static hipError_t launch_enum_m(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
-    constexpr int V1 = M > 0 ? 1 : 0, V2 = M > 0 ? 2 : 0;
-    if (M > 0 && p.pair) {
+    constexpr int V1 = M > 0 ? 1 : 0, V2 = M > 0 ? 2 : 0, V3 = M > 0 ? 3 : 0;
+    if (M > 0 && p.cdv) {
+        if (p.restab_in_lds) launch_enum_mt<M, true, V3>(p, b, nwg, s);
+        else launch_enum_mt<M, false, V3>(p, b, nwg, s);
+    } else if (M > 0 && p.pair) {
         if (p.restab_in_lds) launch_enum_mt<M, true, V2>(p, b, nwg, s);
         else launch_enum_mt<M, false, V2>(p, b, nwg, s);
     } else if (M > 0 && p.prune) {

@@ -85,3 +85,23 @@ def test_limit_n_in_a_batch(fz):
     assert not res[1]["found"] and res[1]["count"] == len(want16)
     assert res[2]["count"] == len(want16)
     assert res[3]["count"] == len(oracle_store(100, [3, 5, 7]))
+
+
+@pytest.mark.parametrize("n,g", [(N3, G3), (N2, G2), (N16, G16)], ids=["d3", "d2", "d16"])
+def test_limits_without_tables(fz, n, g):
+    """The table-free walk (knob "tables" = 2: no count or work table, the
+    slices cut by splitWork from the whole lexicographic range) at the size
+    limits: count, histogram and predicate against the oracle's enumeration
+    (stores always place rows by rank and keep their tables)."""
+    want = oracle_store(n, g)
+    lens = want.astype(np.int64).sum(axis=1)
+    try:
+        fz.config_set("tables", 2)
+        assert fz.count(n, g) == len(want)
+        h, lo, hi = fz.length_hist(n, g)
+        assert (lo, hi) == (int(lens.min()), int(lens.max()))
+        assert np.array_equal(h, np.bincount(lens, minlength=len(h)).astype(np.uint64))
+        assert fz.exists(n, g, int(lens.min())) and fz.exists(n, g, int(lens.max()))
+        assert not fz.exists(n, g, int(lens.max()) + 1)
+    finally:
+        fz.config_set("tables", 0)

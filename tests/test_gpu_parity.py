@@ -242,11 +242,13 @@ with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ta
 
 
 
-# Histogram bins: one LDS set per workgroup up to 8192 bins, global atomics
-# beyond; both sides of that bound and of 2048 (the bound of per-wave bins),
-# and a dense set whose runs collide in few bins across a workgroup's waves.
+# Histogram bins: one LDS set per workgroup up to 8191 bins (and a spare
+# bin), global atomics beyond; both sides of that bound and of 2048 (the
+# bound of per-wave bins), and a dense set whose runs collide in few bins
+# across a workgroup's waves.
 @pytest.mark.parametrize("n,g", [
     (6143, [3, 100, 101, 103]), (6144, [3, 100, 101, 103]),
+    (24572, [3, 1000, 1001, 1003]),
     (24575, [3, 1000, 1001, 1003]), (24576, [3, 1000, 1001, 1003]),
     (30000, [5, 11, 13, 17]), (12000, [6, 11, 13, 17, 19]),
 ])
@@ -331,3 +333,71 @@ def test_single_large_store_prefix(fz):
         assert np.array_equal(out[p:p + 1000].cpu().numpy().view(np.uint32), want), p
     del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("order", [0, 1], ids=["descending", "caller"])
+def test_without_tables(fz, order):
+    """The table-free walk (knob "tables" = 2): slices cut by splitWork with
+    no count or work table, on tiny inputs, the edge cases, the sparse sets
+    and the d=4 query, every order-free consumer against the oracle."""
+    from fzcheck import check_against_oracle
+    cases = tiny_cases(23, 60) + EDGE + SPARSE[:3] + [(10000, [11, 13, 17, 23])]
+    try:
+        fz.config_set("tables", 2)
+        fz.config_set("walk_order", order)
+        for n, g in cases:
+            for mode in ("count", "hist", "exists"):
+                q = dict(n=n, g=g, mode=mode, target_len=n // max(g) + 1)
+                if mode == "count":
+                    r = dict(status=0, count=fz.count(n, g))
+                elif mode == "hist":
+                    h, lo, hi = fz.length_hist(n, g)
+                    r = dict(status=0, bins=h, min_len=lo, max_len=hi, count=int(h.sum()))
+                else:
+                    r = dict(status=0, found=fz.exists(n, g, q["target_len"]))
+                check_against_oracle(q, r)
+    finally:
+        fz.config_set("tables", 0)
+        fz.config_set("walk_order", 0)
+
+
+def test_large_count_without_tables(fz):
+    w = GOLD["single_large"]
+    try:
+        fz.config_set("tables", 2)
+        assert fz.count(w["n"], w["g"]) == w["count"]
+        ls = GOLD["length_set"]
+        h, lo, hi = fz.length_hist(ls["n"], ls["g"])
+        assert np.array_equal(h, oracle.dp_hist(ls["n"], ls["g"]))
+    finally:
+        fz.config_set("tables", 0)
+
+
+@pytest.mark.parametrize("threads,share", [(4, 0), (4, 200000), (16, 0)])
+def test_hybrid_pool(fz, threads, share):
+    """Hybrid pool (knob "host_threads"): host threads walk the last slices of
+    the work while the device walks the others; count, histogram and
+    predicate against the oracle (share 0: the default share per thread;
+    200000: a fifth of the work on the host)."""
+    from fzcheck import check_against_oracle
+    cases = tiny_cases(29, 40) + EDGE + SPARSE[:2] + [(10000, [11, 13, 17, 23])]
+    try:
+        fz.config_set("host_threads", threads)
+        fz.config_set("host_share_ppm", share)
+        for n, g in cases:
+            for mode in ("count", "hist", "exists"):
+                q = dict(n=n, g=g, mode=mode, target_len=n // max(g) + 1)
+                if mode == "count":
+                    r = dict(status=0, count=fz.count(n, g))
+                elif mode == "hist":
+                    h, lo, hi = fz.length_hist(n, g)
+                    r = dict(status=0, bins=h, min_len=lo, max_len=hi, count=int(h.sum()))
+                else:
+                    r = dict(status=0, found=fz.exists(n, g, q["target_len"]))
+                check_against_oracle(q, r)
+        if threads == 16:
+            w = GOLD["single_large"]
+            assert fz.count(w["n"], w["g"]) == w["count"]
+    finally:
+        fz.config_set("host_threads", 0)
+        fz.config_set("host_share_ppm", 0)
