@@ -286,7 +286,12 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * a single query with tables: that many host threads, 0..64, walk the last
  * slices of the work while the device walks the others; 0: off) and
  * "host_share_ppm" (their share of the modelled work in millionths, up to
- * 500000; 0: 3 per thread, about a host thread's rate against the device's).
+ * 500000; 0: 3 per thread, about a host thread's rate against the device's),
+ * "trailing" (Sec. 6.1, dynamic behavior: 1: count and store of a single
+ * query with d >= 4 walked without row skipping or pair table take each full
+ * row's elements Z(R, (g_{d-2}, g_{d-1}, g_d)) at once -- the count from the
+ * count table, the store by copying them from a table of every Z(x) up to
+ * the largest x whose elements fit in 2 GiB; 0: off).
  * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */

@@ -34,6 +34,8 @@ constexpr uint64_t kTableBudget = 64ull << 30;
 // ~3e12 on MI355X, so each thread takes about 3 millionths of the work.
 constexpr uint32_t kHostPpmPerThread = 3;
 constexpr uint32_t kMaxHostThreads = 64;
+// Trailing-index tables of a store: at most 2 GiB of triples.
+constexpr uint64_t kTrailBytes = 2ull << 30;
 constexpr size_t kLdsHistBudget = 64 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
 // per-wave LDS histogram in batches, 8 KB per wave: 1024 64-bit bins, or
@@ -63,6 +65,7 @@ struct Ctx {
     hipStream_t stream = nullptr;
     FzCtl *host_ctl = nullptr; // pinned
     DevBuf S, C, restab, bounds, base, recs, ctl, hist_rows, hist, ranks, rows_out, pt, dpart;
+    DevBuf trail_o, trail_t; // trailing tables of a store (knob "trailing")
     BatchSlot batch; // fz_batch
     bool last_batch = false; // fz_last_slices reads the batch's items
     fz_stats last{};
@@ -90,6 +93,7 @@ uint32_t g_variant = 0; // 1: the variant walk (common-divisor skip, closed-form
 uint32_t g_tables = 0;  // 0: count tables unless above kTableBudget, 1: always, 2: never
 uint32_t g_host_threads = 0; // hybrid pool: host worker threads (0: off)
 uint32_t g_host_ppm = 0;     // their share of the work in millionths (0: kHostPpmPerThread each)
+uint32_t g_trailing = 0;     // 1: trailing-index tables (count and store of the block walk)
 
 bool worth_pruning(const FzPlan &P);
 bool worth_pair(const FzPlan &P);
@@ -410,6 +414,11 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
         P.host_ppm = g_host_ppm ? g_host_ppm : kHostPpmPerThread * g_host_threads;
     }
     set_variant(P);
+    // trailing-index tables: rows of the block walk (d >= 4, no row skipping
+    // or pair table), count and store
+    P.trail = (g_trailing && !P.notab && !P.prune && !P.pair && !P.cdv && P.d >= 4 &&
+               (P.mode == FZM_COUNT || P.mode == FZM_STORE)) ? 1 : 0;
+    P.trail_cap = P.trail && P.mode == FZM_STORE ? kTrailBytes / 12 : 0;
 }
 
 // Bytes of each device buffer a single query of plan P needs.
@@ -477,6 +486,14 @@ int prepare(Ctx &c, FzPlan &P, FzBufs &B, Launch &L)
     B.dpart = (uint64_t *)c.dpart.p;
     B.hist = (uint64_t *)c.hist.p;
     B.out = nullptr;
+    B.TO = nullptr;
+    B.TT = nullptr;
+    if (P.trail && P.mode == FZM_STORE) {
+        FZ_TRY(ensure(c.trail_o, ((size_t)P.stride + 1) * 8));
+        FZ_TRY(ensure(c.trail_t, (size_t)P.trail_cap * 12));
+        B.TO = (uint64_t *)c.trail_o.p;
+        B.TT = (uint32_t *)c.trail_t.p;
+    }
     return FZ_OK;
 }
 
@@ -554,6 +571,7 @@ void host_walk(const FzPlan &P, const uint32_t *b0, const uint32_t *b1, HostPart
 int run_query(Ctx &c, FzPlan &P, FzBufs &B, const Launch &L, hipStream_t s)
 {
     if (!P.notab) FZ_LAUNCH("dp", s, fzk_launch_dp(P, B, s));
+    if (P.trail && P.mode == FZM_STORE) FZ_LAUNCH("trail", s, fzk_launch_trail(P, B, s));
     FZ_LAUNCH("restab", s, fzk_launch_restab(P, B, s));
     if (P.notab) FZ_LAUNCH("slices", s, fzk_launch_split(P, B, s));
     else FZ_LAUNCH("slices", s, fzk_launch_slices(P, B, s));
@@ -1256,6 +1274,7 @@ int do_count_noalloc(uint64_t n, const uint32_t *g, uint32_t d, uint64_t *count,
     Launch L;
     plan_launch(a->cus, P, L);
     P.host_slices = P.host_ppm = 0; // the device walks every slice here
+    P.trail = 0;
     const ScratchSizes z = scratch_sizes(P, L);
     // 256-byte aligned pieces of the array, in a fixed order
     size_t off = 0;
@@ -1505,6 +1524,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "host_threads") == 0 && value <= kMaxHostThreads)
         g_host_threads = (uint32_t)value;
     else if (std::strcmp(key, "host_share_ppm") == 0 && value <= 500000) g_host_ppm = (uint32_t)value;
+    else if (std::strcmp(key, "trailing") == 0 && value <= 1) g_trailing = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

@@ -80,6 +80,13 @@ struct FzPlan {
     // the device walks slices 0..W-1 (n_slices = W).
     uint32_t host_slices;
     uint32_t host_ppm;
+    // Trailing-index tables (Sec. 6.1, knob "trailing"): a full row whose
+    // remainder R is below ctl->trail_m takes its elements from Z(R, (G2,
+    // A, B)) at once -- the count table's row M for the count, a table of
+    // the triples (a_{d-2}, a_{d-1}, a_d) of every Z(x), x <= trail_m, for
+    // the store (at most trail_cap triples).
+    uint32_t trail;
+    uint64_t trail_cap;
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag
@@ -91,6 +98,7 @@ struct FzCtl {
     uint32_t pad1[31];
     uint32_t status;     // FZS_* bits
     uint32_t slices;     // slices cut: W, or fewer for a small query
+    uint64_t trail_m;    // trailing tables: rows with remainder < trail_m take them
     uint64_t total;      // |Z| from the count table
     uint64_t count;      // elements the walkers visited
     uint64_t rows, prefixes;
@@ -124,6 +132,8 @@ struct FzBufs {
     uint32_t *PE;         //   up to n+1 representable remainders
     uint32_t *PO;         //   min(G2, n+1) + 1 chain starts
     uint64_t *dpart;      // FZK_DP_UNITS block sums of the table scans
+    uint64_t *TO;         // trailing tables: TO[x] = first triple of Z(x) in TT, x <= n + 1
+    uint32_t *TT;         //   the triples, 3 words each
 };
 
 // ---------------------------------------------------------------------------
@@ -194,6 +204,7 @@ hipError_t fzk_launch_dp(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_restab(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_slices(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_split(const FzPlan &p, const FzBufs &b, hipStream_t s);
+hipError_t fzk_launch_trail(const FzPlan &p, const FzBufs &b, hipStream_t s);
 hipError_t fzk_launch_enum(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s);
 hipError_t fzk_launch_finalize(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s);
 hipError_t fzk_launch_unrank(const FzPlan &p, const FzBufs &b, const uint64_t *ranks,

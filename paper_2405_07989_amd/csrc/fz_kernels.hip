@@ -530,6 +530,9 @@ struct WalkIO {
     const uint64_t *PC; // pair table (P.pair): representable remainders up to v, per chain
     const uint32_t *PE; //   the representable remainders, ascending per chain
     const uint32_t *PO; //   where each chain's list starts in PE
+    const uint64_t *TO; // trailing tables (P.trail): offsets and triples
+    const uint32_t *TT;
+    uint64_t trail_m;   //   full rows with remainder < trail_m take them
 };
 
 struct WalkOut {
@@ -724,6 +727,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
     uint64_t lane_el = 0;
     uint32_t lane_pref = 0;
     uint64_t lane_pref64 = 0; // lane prefixes of the rows of the block walk
+    uint64_t n_trail = 0;     // elements of rows counted from the count table
     // BLOCKS: a compile-time depth and no row skipping (see the block walk)
     constexpr bool BLOCKS = FIXED && !PRUNE && !PAIR && MAXM > 0;
     uint64_t n_el = 0, n_rows = 0;
@@ -896,6 +900,41 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
             return false;
         };
 
+        // Store from the trailing tables: the row a[0..M-1] with remainder Rr
+        // gets the triples of Z(Rr), 64 rows at a time staged in LDS and
+        // written as consecutive words.  Returns true at the store's limit.
+        auto copy_row = [&](const uint32_t Rr) -> bool {
+            const uint64_t o0 = readlane64(io.TO[Rr], 0), o1 = readlane64(io.TO[Rr + 1], 0);
+            const uint64_t cnt = o1 - o0;
+            const uint64_t lim = P.max_tuples;
+            const uint32_t du = P.d_user;
+            for (uint64_t p0 = 0; p0 < cnt && rank + p0 < lim; p0 += FZK_WAVE) {
+                const uint64_t left = cnt - p0 < lim - rank - p0 ? cnt - p0 : lim - rank - p0;
+                const uint32_t nb2 = left < FZK_WAVE ? (uint32_t)left : FZK_WAVE;
+                if (lane < nb2) {
+                    const uint32_t *tr = io.TT + 3 * (o0 + p0 + lane);
+                    uint32_t *st_row = io.s_stage + lane * du;
+#pragma unroll
+                    for (int q = 0; q < MAXM; ++q) st_row[q] = a[q]; // d >= 4: no virtual coordinate
+                    st_row[MAXM] = tr[0];
+                    st_row[MAXM + 1] = tr[1];
+                    st_row[MAXM + 2] = tr[2];
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                uint32_t *dst = io.out + (rank + p0) * du;
+                const uint32_t words = nb2 * du;
+                for (uint32_t i = lane; i < words; i += FZK_WAVE) dst[i] = io.s_stage[i];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            }
+            if (rank < lim) n_el += (cnt < lim - rank) ? cnt : (lim - rank);
+            rank += cnt;
+            return rank >= lim;
+        };
+
         // BLOCKS (a compile-time depth, no row skipping): the rows of the
         // deepest row level are prepared up to 64 at a time, one per lane --
         // the row's last x and its first chunk's remainder split Rc = Qc B +
@@ -1008,6 +1047,27 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                         if (uni(f)) {
                             done = true;
                             break;
+                        }
+                    }
+                    if constexpr ((MODE == FZM_COUNT || MODE == FZM_STORE) && !CDV) {
+                        // trailing-index tables: a full row (not the slice's
+                        // first row begun mid-way, nor its last) with a small
+                        // remainder takes Z(R, (G2, A, B)) at once
+                        if (P.trail && (j != 0 || xs == 0) && !(end_here && j + 1 == nb)) {
+                            const uint32_t Rr = __builtin_amdgcn_readlane(R, j);
+                            if constexpr (MODE == FZM_COUNT) {
+                                const uint64_t z = io.S[(uint64_t)(P.d - 3) * P.stride + Rr];
+                                n_trail += readlane64(z, 0);
+                                continue;
+                            } else {
+                                if ((uint64_t)Rr < io.trail_m) {
+                                    if (copy_row(Rr)) {
+                                        done = true;
+                                        break;
+                                    }
+                                    continue;
+                                }
+                            }
                         }
                     }
                     // the lane's table entry as a byte offset: rho * 8, rho in
@@ -1212,7 +1272,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
         }
     }
     WalkOut o;
-    o.elements = MODE == FZM_STORE ? n_el : wave_sum64(lane_el);
+    o.elements = MODE == FZM_STORE ? n_el : wave_sum64(lane_el) + n_trail;
     o.rows = n_rows;
     o.prefixes = wave_sum64(lane_pref + lane_pref64);
     return o;
@@ -1253,6 +1313,9 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.PC = Bf.PC;
     io.PE = Bf.PE;
     io.PO = Bf.PO;
+    io.TO = Bf.TO;
+    io.TT = Bf.TT;
+    io.trail_m = P.trail ? Bf.ctl->trail_m : 0;
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) { // one set of bins for the workgroup's waves
             io.wbins = (uint64_t *)scratch;
@@ -1525,6 +1588,100 @@ __global__ void fz_split_round_kernel(FzPlan P, FzBufs Bf, uint32_t r)
         for (uint32_t i = 0; i < K; ++i) c[i] = Bf.bounds[(uint64_t)hi * K + i]; // empty
 }
 
+
+// ---------------------------------------------------------------------------
+// Trailing-index tables (Sec. 6.1, "dynamic behavior").  The elements of a
+// row (a_1 .. a_{d-3}) with remainder R are (a_1 .. a_{d-3}, c) for every c
+// in Z(R, (G2, A, B)): a full row with R <= m takes them at once.  The count
+// reads |Z(R, (G2, A, B))| from the count table's row M (m = n); the store
+// copies them from a table of every Z(x), x < m, ascending, 3 words each,
+// with TO[x] = the first triple of Z(x) (the exclusive sum of row M), m - 1
+// the largest x whose triples fit in P.trail_cap.
+// ---------------------------------------------------------------------------
+// TO[0..n+1] by one workgroup (block sums, then each thread's block), and m.
+__global__ void __launch_bounds__(1024) fz_trail_scan_kernel(FzPlan P, FzBufs Bf)
+{
+    __shared__ uint64_t part[1024];
+    const uint32_t M = P.d - 3;
+    const uint64_t *SM = Bf.S + (uint64_t)M * P.stride;
+    const uint64_t len = (uint64_t)P.n + 1;
+    const uint64_t per = (len + blockDim.x - 1) / blockDim.x;
+    const uint64_t b0 = per * threadIdx.x, b1 = b0 + per < len ? b0 + per : len;
+    // saturating sums: the offsets stay non-decreasing, and the table only
+    // ever holds the x whose offsets are below the cap
+    uint64_t s = 0;
+    for (uint64_t v = b0; v < b1; ++v) s = sat_add(s, SM[v]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t acc = 0;
+        for (uint32_t i = 0; i < blockDim.x; ++i) {
+            const uint64_t t = part[i];
+            part[i] = acc;
+            acc = sat_add(acc, t);
+        }
+    }
+    __syncthreads();
+    uint64_t acc = part[threadIdx.x];
+    for (uint64_t v = b0; v < b1; ++v) {
+        Bf.TO[v] = acc;
+        acc = sat_add(acc, SM[v]);
+    }
+    if (b1 == len && b0 < b1) Bf.TO[len] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) { // the largest m whose triples fit
+        uint64_t lo = 0, hi = len; // TO[lo] fits; find the last x with TO[x + 1] <= cap
+        if (Bf.TO[1] > P.trail_cap) {
+            Bf.ctl->trail_m = 0; // not even Z(0): no row takes the table
+        } else {
+            while (hi - lo > 1) {
+                const uint64_t mid = (lo + hi) / 2;
+                if (Bf.TO[mid + 1] <= P.trail_cap) lo = mid;
+                else hi = mid;
+            }
+            Bf.ctl->trail_m = lo + 1; // Z(x) for every x < trail_m
+        }
+    }
+}
+
+// The triples of Z(x), x < m: a wave per x, lanes over c = a_{d-2}; each
+// lane's pair elements run from the first valid a_{d-1}, positions from a
+// wave scan of the lanes' counts.
+__global__ void fz_trail_fill_kernel(FzPlan P, FzBufs Bf)
+{
+    const uint64_t m = Bf.ctl->trail_m; // the table holds Z(x), x < m
+    const uint32_t lane = __lane_id();
+    const uint32_t waves = gridDim.x * (blockDim.x / FZK_WAVE);
+    for (uint64_t x = blockIdx.x * (blockDim.x / FZK_WAVE) + threadIdx.x / FZK_WAVE; x < m;
+         x += waves) {
+        uint64_t pos = Bf.TO[x];
+        const uint32_t cmax = (uint32_t)x / P.G2;
+        for (uint32_t c0 = 0; c0 <= cmax; c0 += FZK_WAVE) {
+            const uint32_t c = c0 + lane;
+            uint32_t cnt = 0, t0 = 0, e0 = 0;
+            if (c <= cmax) {
+                const uint32_t R = (uint32_t)x - c * P.G2;
+                if (R % P.D == 0) {
+                    t0 = (uint32_t)((uint64_t)((R / P.D) % P.ord) * P.inv % P.ord);
+                    if ((uint64_t)P.A * t0 <= R) {
+                        e0 = (R - P.A * t0) / P.B;
+                        cnt = e0 / P.delta + 1;
+                    }
+                }
+            }
+            const uint64_t incl = wave_incl_scan64(cnt, lane);
+            const uint64_t tot = readlane64(incl, FZK_WAVE - 1);
+            uint32_t *dst = Bf.TT + 3 * (pos + incl - cnt);
+            for (uint32_t k = 0; k < cnt; ++k) {
+                dst[3 * k] = c;
+                dst[3 * k + 1] = t0 + k * P.ord;
+                dst[3 * k + 2] = e0 - k * P.delta;
+            }
+            pos += tot;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Element of each requested rank (fz_unrank): the slice-bound search carried
 // through all d coordinates.  A rank >= |Z| sets FZS_MISMATCH and leaves its
@@ -1780,6 +1937,9 @@ __global__ void __launch_bounds__(FZK_WG)
             io.S = B.tables + Q.s_off; // read only when P.prune (set for cut queries)
             io.PC = nullptr;
             io.PE = io.PO = nullptr;
+            io.TO = nullptr; // (no trailing tables in a batch)
+            io.TT = nullptr;
+            io.trail_m = 0;
             io.wbins = nullptr;
             io.wbins32 = nullptr;
             const uint32_t lds_hist = mode == FZM_HIST ? uni(P.hist_in_lds) : 0u;
@@ -1923,6 +2083,14 @@ hipError_t fzk_launch_split(const FzPlan &p, const FzBufs &b, hipStream_t s)
     if (p.mode == FZM_HIST)
         hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.hist,
                            (uint64_t)p.nbins + 1); // and the spare bin
+    return hipGetLastError();
+}
+
+hipError_t fzk_launch_trail(const FzPlan &p, const FzBufs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(fz_trail_scan_kernel, dim3(1), dim3(1024), 0, s, p, b);
+    if (p.mode == FZM_STORE)
+        hipLaunchKernelGGL(fz_trail_fill_kernel, dim3(2048), dim3(256), 0, s, p, b);
     return hipGetLastError();
 }
 
