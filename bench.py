@@ -143,29 +143,54 @@ def measure_batch(fz, reps=3):
     w = fzinputs.load_golden()["batch"]["queries"]
     qs = [dict(n=q["n"], g=q["g"], mode=q["mode"], target_len=q["target_len"]) for q in w]
     fz.batch(qs[:64])
-    times, walk, prep = [], [], []
-    for r in range(reps):
-        fz.profile_reset()
-        fz.profile_enable(True)
-        t0 = time.perf_counter()
-        res = fz.batch(qs)
-        times.append(time.perf_counter() - t0)
-        fz.profile_enable(False)
-        prep.append(fz.profile_read("batch.tables")[0] + fz.profile_read("batch.slices")[0])
-        walk.append(fz.profile_read("batch.walk")[0])
-        for q, x, ww in zip(qs, res, w):
-            ok = x["status"] == 0 and (x["count"] == ww["count"] or
-                                       (q["mode"] == "exists" and x["found"]))
-            if not ok:
-                raise RuntimeError(f"batch: wrong result for {q}: {x}")
-        log(f"batch rep {r + 1}/{reps}: {times[-1] * 1e3:.1f} ms")
-    t = sorted(times)[len(times) // 2]
+
+    def timed(label):
+        times, walk, prep = [], [], []
+        for r in range(reps):
+            fz.profile_reset()
+            fz.profile_enable(True)
+            t0 = time.perf_counter()
+            res = fz.batch(qs)
+            times.append(time.perf_counter() - t0)
+            fz.profile_enable(False)
+            st = fz.last_stats()
+            prep.append(fz.profile_read("batch.tables")[0] + fz.profile_read("batch.slices")[0])
+            walk.append(fz.profile_read("batch.walk")[0])
+            for q, x, ww in zip(qs, res, w):
+                ok = x["status"] == 0 and (x["count"] == ww["count"] or
+                                           (q["mode"] == "exists" and x["found"]))
+                if not ok:
+                    raise RuntimeError(f"batch: wrong result for {q}: {x}")
+            log(f"batch ({label}) rep {r + 1}/{reps}: {times[-1] * 1e3:.1f} ms")
+        t = sorted(times)[len(times) // 2]
+        wk = sorted(walk)[len(walk) // 2]
+        # the walker's algorithmic int32 work, as for the single query
+        ops = OPS_PER_ELEMENT * st["elements"] + OPS_PER_PREFIX * st["prefixes"]
+        return {"ms": t * 1e3, "queries_per_s": len(qs) / t,
+                "factorizations_per_s": elements / t,
+                "prep_ms": sorted(prep)[len(prep) // 2], "walk_ms": wk,
+                "walker_stats": st,
+                "roofline": {"bound": "alu", "achieved": ops / (wk / 1e3) / 1e12,
+                             "peak": PEAK_INT32_OPS / 1e12, "unit": "Tops/s (int32)",
+                             "frac": ops / (wk / 1e3) / PEAK_INT32_OPS, "ops": ops}}
+
     elements = sum(x["count"] for x in w)
-    return {"queries": len(qs), "ms": t * 1e3, "queries_per_s": len(qs) / t,
-            "factorizations_per_s": elements / t,
-            "prep_ms": sorted(prep)[len(prep) // 2], "walk_ms": sorted(walk)[len(walk) // 2],
-            "workload": "4096 queries: d in 3..8, generators in [5,1000], n log-uniform in "
-                        "[1e3,1e6], |Z| <= 1e8, consumer count/hist/exists"}
+    out = {"queries": len(qs),
+           "workload": "4096 queries: d in 3..8, generators in [5,1000], n log-uniform in "
+                       "[1e3,1e6], |Z| <= 1e8, consumer count/hist/exists"}
+    out["default"] = timed("default slices")
+    # the autotuner picks slices per wave and workgroups per CU on this batch
+    tune = fz.autotune(qs, reps=1)
+    out["autotune"] = {k: tune[k] for k in ("slices_per_wave", "workgroups_per_cu", "candidates")}
+    try:
+        out["tuned"] = timed("tuned")
+    finally:
+        fz.config_set("slices_per_wave", 0)
+        fz.config_set("workgroups_per_cu", 0)
+    best = min(out["default"], out["tuned"], key=lambda x: x["ms"])
+    out.update({k: best[k] for k in ("ms", "queries_per_s", "factorizations_per_s", "prep_ms",
+                                     "walk_ms")})
+    return out
 
 
 def measure_single_small(fz, torch, reps=200):
@@ -196,6 +221,40 @@ def measure_single_small(fz, torch, reps=200):
         res[f"{mode}_factorizations_per_s"] = N / percentile(lat, 0.5)
     del out
     return res
+
+
+def measure_variant(fz, n, g, N, ls, reps=3):
+    """The variant walk (knob "variant" = 1; not the metric): the count of the
+    d=6 query in drawn and in descending generator order and the length-set
+    histogram, with the common-divisor skip over the last two and three
+    generators and closed-form run lengths.  Kernel time of the walker,
+    results checked against the stored counts."""
+    out = {"what": "common-divisor skip over the last 2 and 3 generators (Sec. 3.2.4) + "
+                   "closed-form run lengths; reported beside the metric, not as it"}
+    fz.config_set("variant", 1)
+    try:
+        for label, order, fn, key, want in [
+                ("count_drawn_order", 1, lambda: fz.count(n, g), "enum.count", N),
+                ("count_descending_order", 0, lambda: fz.count(n, g), "enum.count", N),
+                ("length_set_hist", 0, lambda: int(fz.length_hist(ls["n"], ls["g"])[0].sum()),
+                 "enum.hist", ls["count"])]:
+            fz.config_set("walk_order", order)
+            fn()
+            fz.profile_reset()
+            fz.profile_enable(True)
+            for _ in range(reps):
+                if fn() != want:
+                    raise RuntimeError(f"variant walk: wrong result ({label})")
+            fz.profile_enable(False)
+            ms, k = fz.profile_read(key)
+            st = fz.last_stats()
+            out[label] = {"avg_launch_ms": ms / max(k, 1),
+                          "factorizations_per_s": want / (ms / 1e3 / max(k, 1)),
+                          "rows": st["rows"], "prefixes": st["prefixes"]}
+    finally:
+        fz.config_set("variant", 0)
+        fz.config_set("walk_order", 0)
+    return out
 
 
 def _serve(fz, qs, gaps=None, inflight=4):
@@ -468,6 +527,10 @@ def main():
         "walker_stats": st_ls,
     }
     log("length-set histogram done")
+    res["variant_walk"] = measure_variant(fz, n, g, N, ls)
+    log("variant walk: count drawn %.2f ms, length-set histogram %.1f ms" % (
+        res["variant_walk"]["count_drawn_order"]["avg_launch_ms"],
+        res["variant_walk"]["length_set_hist"]["avg_launch_ms"]))
     res["single_small"] = measure_single_small(fz, torch)
     log("single small query: count p50 %.0f us, store p50 %.0f us" % (
         res["single_small"]["count_p50_us"], res["single_small"]["store_p50_us"]))
