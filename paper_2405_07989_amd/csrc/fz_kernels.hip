@@ -1166,11 +1166,12 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
             }
             const int32_t xlast = last ? xe - 1 : xhi;
             ++n_rows;
-            if constexpr (MODE == FZM_EXISTS) {
-                const uint32_t f =
+            // the predicate's flag is loaded here and looked at once the row
+            // is walked, so that its latency overlaps the row's first loads
+            uint32_t found_flag = 0;
+            if constexpr (MODE == FZM_EXISTS)
+                found_flag =
                     __hip_atomic_load(io.found, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (uni(f)) break;
-            }
             if constexpr (PAIR) {
                 // Only the lane prefixes with an element: the pair remainders
                 // v = Rp - x G2 (x in [xs, xlast]) that the last pair
@@ -1211,30 +1212,47 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     Qc = fdiv(Rc, P.div_B);
                     Pc = Rc - Qc * P.B;
                 }
-                for (int32_t c = xs; c <= xlast; c += FZK_WAVE) {
-                    const bool active = (int32_t)lane <= xlast - c;
-                    const uint32_t rho2 = Pc + lr2;
+                // The next chunk's table entry is loaded before this chunk is
+                // consumed, so that its latency overlaps the consumer's work
+                // (a sparse row has many chunks with little to consume).
+                // left = xlast - c counts the lanes still to come (no signed
+                // overflow near the size limit, where c + 64 would wrap).
+                int2 ent;
+                if (xs <= xlast) {
+                    const uint32_t ti = (int32_t)lane <= xlast - xs ? Pc + lr2 : 0u;
+                    ent = TLDS ? io.ltab[ti] : io.gtab[ti];
+                }
+                uint32_t c = (uint32_t)xs;
+                for (int32_t left = xlast - xs; left >= 0; left -= FZK_WAVE, c += FZK_WAVE) {
+                    const bool active = (int32_t)lane <= left;
                     const int32_t q2 = (int32_t)(Qc - lq1);
-                    const uint32_t ti = active ? rho2 : 0u;
-                    const int2 ent = TLDS ? io.ltab[ti] : io.gtab[ti];
+                    uint32_t Pn = Pc - c64r, Qn = Qc - c64q;
+                    if ((int32_t)Pn < 0) {
+                        Pn += P.B;
+                        Qn -= 1;
+                    }
+                    int2 entn = ent;
+                    if (left >= FZK_WAVE) {
+                        const uint32_t ti = (int32_t)lane <= left - FZK_WAVE ? Pn + lr2 : 0u;
+                        entn = TLDS ? io.ltab[ti] : io.gtab[ti];
+                    }
                     // a lane with no element starts at -1, so that the common
                     // decrement stays above -(n + 2 A) > -2^31 for every lane
                     int32_t ad0 = q2 - ent.y;
                     ad0 = (active && ad0 >= 0) ? ad0 : -1;
                     lane_pref += active ? 1u : 0u;
-                    if (consume((uint32_t)c + lane, (uint32_t)ent.x, ad0, c, false)) {
+                    if (consume(c + lane, (uint32_t)ent.x, ad0, (int32_t)c, false)) {
                         done = true;
                         break;
                     }
-                    Pc -= c64r;
-                    Qc -= c64q;
-                    if ((int32_t)Pc < 0) {
-                        Pc += P.B;
-                        Qc -= 1;
-                    }
+                    ent = entn;
+                    Pc = Pn;
+                    Qc = Qn;
                 }
             }
             if (done || last) break;
+            if constexpr (MODE == FZM_EXISTS)
+                if (uni(found_flag)) break;
             // next row.  Usually the deepest level grows by one (with a
             // compile-time depth, tested first without the general scan).
             if constexpr (FIXED && MAXM > 0) {
