@@ -87,6 +87,10 @@ struct FzPlan {
     // the store (at most trail_cap triples).
     uint32_t trail;
     uint64_t trail_cap;
+    // Packed walk of short rows (pack = 1; count, histogram and predicate,
+    // d >= 4): the lane prefixes of up to 64 consecutive rows of the deepest
+    // row level fill the chunks end to end.
+    uint32_t pack;
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag

@@ -696,7 +696,12 @@ __device__ __forceinline__ void count_steps(uint32_t &cnt, int32_t &ad, int32_t 
 // CDV: the variant walk of the block walker (common-divisor skip over the
 // last two and three generators, Sec. 3.2.4, and each lane's run counted in
 // closed form): neighbouring lanes are sx apart in x and block rows sy apart.
-template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED, bool CDV = false>
+// PACK: the packed walk of short rows (count, histogram, predicate): the lane
+// prefixes of up to 64 rows of the deepest row level are laid end to end and
+// walked 64 at a time, so that a chunk is not one row's few prefixes.  (With
+// no row level, M = 0, the one row is walked alone.)
+template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED, bool CDV = false,
+          bool PACK = false>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                                               const uint32_t *b0, const uint32_t *b1,
                                               uint64_t rank, const WalkIO &io, uint32_t lane)
@@ -729,7 +734,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
     uint64_t lane_pref64 = 0; // lane prefixes of the rows of the block walk
     uint64_t n_trail = 0;     // elements of rows counted from the count table
     // BLOCKS: a compile-time depth and no row skipping (see the block walk)
-    constexpr bool BLOCKS = FIXED && !PRUNE && !PAIR && MAXM > 0;
+    constexpr bool BLOCKS = FIXED && !PRUNE && !PAIR && !PACK && MAXM > 0;
+    static_assert(!PACK || (MAXM > 0 && !PAIR && !CDV && MODE != FZM_STORE),
+                  "the packed walk serves order-free consumers");
     uint64_t n_el = 0, n_rows = 0;
     if (uni(b0[0]) != FZK_SENTINEL) {
         uint32_t a[MAXM > 0 ? MAXM : 1];
@@ -786,7 +793,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 int32_t ad = ad0;
                 if constexpr (CDV) { // the run's length in closed form
                     cnt = ad0 >= 0 ? fdiv((uint32_t)ad0, P.div_delta) + 1u : 0u;
-                } else if constexpr (BLOCKS) {
+                } else if constexpr (BLOCKS || PACK) {
                     count_steps(cnt, ad, delta, delta2);
                 } else if (__ballot(ad >= 0)) {
                     do {
@@ -804,7 +811,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 int32_t ad = ad0;
                 if constexpr (CDV) { // the run's length in closed form
                     cnt = ad0 >= 0 ? fdiv((uint32_t)ad0, P.div_delta) + 1u : 0u;
-                } else if constexpr (BLOCKS) {
+                } else if constexpr (BLOCKS || PACK) {
                     count_steps(cnt, ad, delta, delta2);
                 } else if (__ballot(ad >= 0)) {
                     do {
@@ -1139,7 +1146,131 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 upper_eq = upper_equal();
             }
         }
-        while (!BLOCKS && !done) {
+        // PACK: rows y = ay + j (j < 64) of the deepest level dl = M - 1, one
+        // per lane: its remainder R_j, its lane prefixes x0_j .. xlast_j (none
+        // when the row has no element: with PRUNE, when S[M][R_j] = 0) and
+        // their exclusive scan, which places the row's prefixes in the block's
+        // stream.  Each chunk of 64 stream positions finds every lane's row
+        // (the rows that begin inside the chunk, one by one) and solves the
+        // lane's x from its remainder alone.
+        if constexpr (PACK) {
+            const uint32_t dl = M - 1;
+            uint32_t gy = 0;
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k)
+                if (k == (int)dl) gy = P.g[k];
+            int pchk = 0; // PRUNE: levels < pchk known to have elements
+            while (!done) {
+                if constexpr (PRUNE) {
+                    // the upper levels must have completions (and the first
+                    // row too: skip_empty moves to the first row that has)
+                    bool moved = false;
+                    if (!skip_empty<MAXM>(P, M, io.S, a, rr, e, end_open, pchk, moved, lane)) break;
+                    if (moved) xs = 0;
+                }
+                uint32_t ay = 0, ey = 0;
+                bool ueq = !end_open; // the upper levels equal the end prefix's
+                plen = 0;
+#pragma unroll
+                for (int k = 0; k < MAXM; ++k) {
+                    if (k == (int)dl) {
+                        ay = a[k];
+                        ey = e[k];
+                    }
+                    if (k < (int)dl) ueq = ueq && a[k] == e[k];
+                    plen += a[k];
+                }
+                const uint32_t R0 = rr[MAXM];
+                const uint64_t off = (uint64_t)lane * gy;
+                bool in = M > 0 ? off <= R0 : lane == 0;
+                if (ueq) in = in && ay + lane <= ey;
+                const uint32_t nb = (uint32_t)__builtin_popcountll(__ballot(in));
+                const bool end_here = ueq && ay + nb - 1 == ey;
+                const uint32_t R = R0 - (uint32_t)off; // meaningful for lanes in
+                const int32_t x0 = lane == 0 ? xs : 0;
+                const int32_t xl_row =
+                    (end_here && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
+                bool has = in && xl_row >= x0;
+                if constexpr (PRUNE)
+                    if (has) has = io.S[(uint64_t)M * P.stride + R] != 0;
+                const uint32_t np = has ? (uint32_t)(xl_row - x0 + 1) : 0u;
+                lane_pref64 += np;
+                const uint64_t excl = wave_incl_scan64(np, lane) - np;
+                const uint64_t T = readlane64(excl + np, FZK_WAVE - 1);
+                const uint32_t exlo = (uint32_t)excl;
+                n_rows += nb;
+                if constexpr (MODE == FZM_EXISTS) {
+                    const uint32_t f = __hip_atomic_load(io.found, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                    if (uni(f)) break;
+                }
+                for (uint64_t p0 = 0; p0 < T; p0 += FZK_WAVE) {
+                    // the row holding position p0 (the last non-empty row
+                    // that begins at or before it), then the rows that begin
+                    // inside the chunk
+                    const uint64_t le = __ballot(np != 0 && excl <= p0);
+                    uint32_t jl = (FZK_WAVE - 1) - (uint32_t)__builtin_clzll(le);
+                    uint64_t st = __ballot(np != 0 && excl > p0 && excl < p0 + FZK_WAVE);
+                    while (st) {
+                        const uint32_t j = (uint32_t)__builtin_ctzll(st);
+                        st &= st - 1;
+                        const uint32_t sj = __builtin_amdgcn_readlane(exlo, j) - (uint32_t)p0;
+                        jl = lane >= sj ? j : jl;
+                    }
+                    const bool active = p0 + lane < T;
+                    const uint32_t Rj = (uint32_t)__shfl((int)R, (int)jl, FZK_WAVE);
+                    const uint32_t ej = (uint32_t)__shfl((int)exlo, (int)jl, FZK_WAVE);
+                    // x = x0_j + (p - excl_j); the lane's remainder Rj - x G2 >= 0
+                    const uint32_t x = (jl == 0 ? (uint32_t)xs : 0u) + ((uint32_t)p0 + lane - ej);
+                    const uint32_t Rc = Rj - x * P.G2;
+                    const uint32_t Qv = fdiv(Rc, P.div_B);
+                    const uint32_t Pv = Rc - Qv * P.B;
+                    const uint32_t ti = active ? Pv + P.B : 0u;
+                    const int2 ent = TLDS ? io.ltab[ti] : io.gtab[ti];
+                    int32_t ad0 = (int32_t)(Qv - 1) - ent.y;
+                    ad0 = (active && ad0 >= 0) ? ad0 : -1;
+                    // the row's length offset jl rides on x (plen is row 0's)
+                    if (consume(x + jl, (uint32_t)ent.x, ad0, 0, false)) {
+                        done = true;
+                        break;
+                    }
+                }
+                if (done || (ueq && ay + nb > ey) || M == 0) break;
+                // the block's last row, then the next row of the deepest
+                // level, else of a shallower one
+                uint32_t ylast = ay + nb - 1, rlast = R0 - (nb - 1) * gy;
+                xs = 0;
+                if (rlast >= gy) {
+                    ylast += 1;
+                    rlast -= gy;
+#pragma unroll
+                    for (int k = 0; k < MAXM; ++k)
+                        if (k == (int)dl) a[k] = ylast;
+#pragma unroll
+                    for (int k = 1; k <= MAXM; ++k)
+                        if (k > (int)dl) rr[k] = rlast;
+                    pchk = (int)dl;
+                    continue;
+                }
+                int kk = -1;
+#pragma unroll
+                for (int k = 0; k < MAXM; ++k)
+                    if (k < (int)dl && rr[k + 1] >= P.g[k]) kk = k;
+                if (kk < 0) break;
+#pragma unroll
+                for (int k = 0; k < MAXM; ++k) {
+                    if (k == kk) {
+                        a[k] += 1;
+                        rr[k + 1] -= P.g[k];
+                    } else if (k > kk) {
+                        a[k] = 0;
+                        rr[k + 1] = rr[k];
+                    }
+                }
+                pchk = kk;
+            }
+        }
+        while (!BLOCKS && !PACK && !done) {
             if (PRUNE && M > 0) {
                 bool moved = false;
                 if (!skip_empty<MAXM>(P, M, io.S, a, rr, e, end_open, chk, moved, lane)) break;
@@ -1368,7 +1499,8 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
         const WalkOut o =
-            walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2), (VAR == 2), true, (VAR == 3)>(
+            walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2 || VAR == 5), (VAR == 2), true,
+                       (VAR == 3), (VAR == 4 || VAR == 5)>(
                 P, M, b0, b0 + NP, Bf.base[s], io, lane);
         {
             FzSliceRec rec;
@@ -1968,13 +2100,22 @@ __global__ void __launch_bounds__(FZK_WG)
                 for (uint32_t i = lane; i < lds_words; i += FZK_WAVE) wb[i] = 0;
             }
             const bool prune = uni(P.prune) != 0;
+            // Order-free consumers take the packed walk, stores the plain one.
+            // (Both walks of a consumer in one kernel would double its
+            // registers.)
 #define FZ_WALK(MD)                                                                                \
     (prune ? walk_slice<MAXM, MD, false, true, false, false>(P, M, b0, b1, base, io, lane)              \
            : walk_slice<MAXM, MD, false, false, false, false>(P, M, b0, b1, base, io, lane))
-            if (mode == FZM_COUNT) o = FZ_WALK(FZM_COUNT);
-            else if (mode == FZM_HIST) o = FZ_WALK(FZM_HIST);
-            else if (mode == FZM_EXISTS) o = FZ_WALK(FZM_EXISTS);
+#define FZ_PACKED(MD)                                                                              \
+    (prune ? walk_slice<MAXM, MD, false, true, false, false, false, true>(P, M, b0, b1, base, io,   \
+                                                                          lane)                    \
+           : walk_slice<MAXM, MD, false, false, false, false, false, true>(P, M, b0, b1, base, io,  \
+                                                                           lane))
+            if (mode == FZM_COUNT) o = FZ_PACKED(FZM_COUNT);
+            else if (mode == FZM_HIST) o = FZ_PACKED(FZM_HIST);
+            else if (mode == FZM_EXISTS) o = FZ_PACKED(FZM_EXISTS);
             else o = FZ_WALK(FZM_STORE);
+#undef FZ_PACKED
 #undef FZ_WALK
             if (lds_hist == 1) {
                 const uint64_t *wb64 = (const uint64_t *)wb;
@@ -2150,9 +2291,11 @@ static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipSt
                            s, p, b);
         break;
     default:
-        // (the variant walk counts runs in closed form: no store)
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_STORE, TLDS, VAR == 3 ? 0 : VAR>), dim3(nwg),
-                           dim3(FZK_WG), lds, s, p, b);
+        // (the variant walk counts runs in closed form, and the packed walk
+        // does not keep rank order: no store)
+        hipLaunchKernelGGL(
+            (fz_enum_kernel<M, FZM_STORE, TLDS, VAR == 3 || VAR == 4 ? 0 : VAR == 5 ? 1 : VAR>),
+            dim3(nwg), dim3(FZK_WG), lds, s, p, b);
         break;
     }
 }
@@ -2163,7 +2306,16 @@ template <int M>
 static hipError_t launch_enum_m(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipStream_t s)
 {
     constexpr int V1 = M > 0 ? 1 : 0, V2 = M > 0 ? 2 : 0, V3 = M > 0 ? 3 : 0;
-    if (M > 0 && p.cdv) {
+    constexpr int V4 = M > 0 ? 4 : 0, V5 = M > 0 ? 5 : 0;
+    if (M > 0 && p.pack) {
+        if (p.prune) {
+            if (p.restab_in_lds) launch_enum_mt<M, true, V5>(p, b, nwg, s);
+            else launch_enum_mt<M, false, V5>(p, b, nwg, s);
+        } else {
+            if (p.restab_in_lds) launch_enum_mt<M, true, V4>(p, b, nwg, s);
+            else launch_enum_mt<M, false, V4>(p, b, nwg, s);
+        }
+    } else if (M > 0 && p.cdv) {
         if (p.restab_in_lds) launch_enum_mt<M, true, V3>(p, b, nwg, s);
         else launch_enum_mt<M, false, V3>(p, b, nwg, s);
     } else if (M > 0 && p.pair) {
