@@ -291,7 +291,11 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * query with d >= 4 walked without row skipping or pair table take each full
  * row's elements Z(R, (g_{d-2}, g_{d-1}, g_d)) at once -- the count from the
  * count table, the store by copying them from a table of every Z(x) up to
- * the largest x whose elements fit in 2 GiB; 0: off).
+ * the largest x whose elements fit in 2 GiB; 0: off), "packed" (count,
+ * histogram and predicate: the lane prefixes of up to 64 consecutive rows
+ * of the deepest row level are walked end to end, 64 at a time; 0: for
+ * sparse sets that skip empty rows, 1: always, 2: never; the batch walker
+ * walks every order-free consumer packed).
  * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */
