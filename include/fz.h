@@ -237,7 +237,8 @@ typedef struct {
 int fz_last_stats(fz_stats *out);
 
 /* Per-slice record of the last successful enumeration on this device: the
- * elements and rows of each slice and the device wall clock (100 MHz ticks)
+ * elements, rows and lane prefixes a_1..a_{d-2} of each slice and the device
+ * wall clock (100 MHz ticks)
  * when a wavefront took it and finished it; for judging the balance of the
  * slice cut.  After fz_batch, the records are the batch's work items, in
  * the order of its work queue.  Copies min(cap, slices)
@@ -245,6 +246,7 @@ int fz_last_stats(fz_stats *out);
 typedef struct {
     uint64_t elements;
     uint64_t rows;
+    uint64_t prefixes;
     uint64_t t_begin;
     uint64_t t_end;
     uint32_t query;     /* fz_batch: index of the query the slice belongs to */

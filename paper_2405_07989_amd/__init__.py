@@ -52,6 +52,7 @@ class fz_stats(ctypes.Structure):
 
 class fz_slice_info(ctypes.Structure):
     _fields_ = [("elements", ctypes.c_uint64), ("rows", ctypes.c_uint64),
+                ("prefixes", ctypes.c_uint64),
                 ("t_begin", ctypes.c_uint64), ("t_end", ctypes.c_uint64),
                 ("query", ctypes.c_uint32), ("slice", ctypes.c_uint32)]
 
@@ -256,38 +257,73 @@ def unrank(n: int, g, ranks):
     return out[: len(r)]
 
 
+def _struct_dtype(cls, kinds):
+    """numpy dtype laid out exactly as the ctypes structure cls."""
+    names = [f for f, _ in cls._fields_]
+    return np.dtype({"names": names, "formats": [kinds[f] for f in names],
+                     "offsets": [getattr(cls, f).offset for f in names],
+                     "itemsize": ctypes.sizeof(cls)})
+
+
+_QUERY_DT = _struct_dtype(fz_query, dict(n=np.uint64, g=np.uint64, d=np.uint32, mode=np.uint32,
+                                         target_len=np.uint64, bins=np.uint64, nbins=np.uint64,
+                                         d_out=np.uint64, max_tuples=np.uint64))
+_RESULT_DT = _struct_dtype(fz_result, dict(status=np.int32, found=np.int32, count=np.uint64,
+                                           total=np.uint64, min_len=np.uint64, max_len=np.uint64,
+                                           written=np.uint64))
+
+
 def _marshal(queries):
     """fz_query array for a list of query dicts (see batch); returns it with
-    the host buffers it points to."""
+    the host buffers it points to.  The array is filled column by column (a
+    batch holds thousands of queries): all generators in one buffer, all
+    histogram bins in another."""
     nq = len(queries)
-    qarr = (fz_query * max(nq, 1))()
-    keep = []
+    qa = np.zeros(max(nq, 1), dtype=_QUERY_DT)
+    gl = [q["g"] for q in queries]
+    ds = np.fromiter((len(g) for g in gl), dtype=np.int64, count=nq)
+    allg = np.fromiter((x for g in gl for x in g), dtype=np.uint32, count=int(ds.sum()))
+    goff = np.zeros(nq, dtype=np.uint64)
+    if nq > 1:
+        np.cumsum(ds[:-1], out=goff[1:], dtype=np.uint64)
+    gbase = allg.ctypes.data if len(allg) else 0
+    if nq:
+        qa["n"][:nq] = [q["n"] for q in queries]
+        qa["g"][:nq] = gbase + 4 * goff
+        qa["d"][:nq] = ds
+        qa["mode"][:nq] = [MODES[q["mode"]] for q in queries]
+        qa["target_len"][:nq] = [q.get("target_len", 0) for q in queries]
+    hist = [i for i, q in enumerate(queries) if q["mode"] == "hist"]
+    nbs = []
+    for i in hist:
+        q = queries[i]
+        nb = q.get("nbins")
+        if not nb:
+            gp = ctypes.cast(gbase + 4 * int(goff[i]), _u32p)
+            nb = max(int(_lib.fz_length_bins(q["n"], gp, int(ds[i]))), 1)
+        nbs.append(nb)
+    bins_all = np.zeros(sum(nbs), dtype=np.uint64)
+    off = 0
+    for i, nb in zip(hist, nbs):
+        bins = bins_all[off:off + nb]
+        queries[i]["_bins"] = bins
+        qa["bins"][i] = bins.ctypes.data
+        qa["nbins"][i] = nb
+        off += nb
     for i, q in enumerate(queries):
-        garr, gp = _gens(q["g"])
-        keep.append(garr)
-        qq = qarr[i]
-        qq.n = q["n"]
-        qq.g = gp
-        qq.d = len(garr)
-        qq.mode = MODES[q["mode"]]
-        qq.target_len = q.get("target_len", 0)
-        if q["mode"] == "hist":
-            nb = q.get("nbins") or max(length_bins(q["n"], q["g"]), 1)
-            bins = np.zeros(nb, dtype=np.uint64)
-            keep.append(bins)
-            qq.bins = bins.ctypes.data_as(_u64p)
-            qq.nbins = nb
-            q["_bins"] = bins
-        if q["mode"] == "store":
-            out = q["out"]
-            if out.dim() != 2 or out.shape[1] != len(garr) or not out.is_contiguous() \
-                    or out.element_size() != 4:
-                raise ValueError("out must be a contiguous [rows, d] tensor of 32-bit integers")
-            qq.d_out = out.data_ptr()
-            qq.max_tuples = q.get("max_tuples", out.shape[0])
-            if qq.max_tuples > out.shape[0]:
-                raise ValueError("max_tuples exceeds the rows of out")
-    return qarr, keep
+        if q["mode"] != "store":
+            continue
+        out = q["out"]
+        if out.dim() != 2 or out.shape[1] != int(ds[i]) or not out.is_contiguous() \
+                or out.element_size() != 4:
+            raise ValueError("out must be a contiguous [rows, d] tensor of 32-bit integers")
+        mt = q.get("max_tuples", out.shape[0])
+        if mt > out.shape[0]:
+            raise ValueError("max_tuples exceeds the rows of out")
+        qa["d_out"][i] = out.data_ptr()
+        qa["max_tuples"][i] = mt
+    qarr = (fz_query * max(nq, 1)).from_buffer(qa)
+    return qarr, [qa, allg, bins_all]
 
 
 def batch(queries, stream=None):
@@ -304,7 +340,8 @@ def batch(queries, stream=None):
     if nq:
         stream = _after_torch(stream)
     _check(_lib.fz_batch(qarr, rarr, nq, _vp(stream) if stream else None), "fz_batch")
-    return [_result_dict(q, rarr[i]) for i, q in enumerate(queries)]
+    res = np.frombuffer(rarr, dtype=_RESULT_DT, count=nq)
+    return [_result_dict(q, r) for q, r in zip(queries, res.tolist())]
 
 
 def autotune(queries, reps: int = 3) -> dict:
@@ -320,13 +357,19 @@ def autotune(queries, reps: int = 3) -> dict:
 
 
 def _result_dict(q, r):
-    d = dict(status=r.status, count=r.count, total=r.total, found=bool(r.found))
+    """Result dict of one query from its fz_result, as a ctypes structure or
+    as a tuple in field order (status, found, count, total, min_len,
+    max_len, written)."""
+    if not isinstance(r, tuple):
+        r = tuple(getattr(r, f) for f, _ in fz_result._fields_)
+    status, found, count, total, min_len, max_len, written = r
+    d = dict(status=status, count=count, total=total, found=bool(found))
     if q["mode"] == "hist":
         d["bins"] = q.pop("_bins", None)
-        d["min_len"] = None if r.min_len == 2**64 - 1 else r.min_len
-        d["max_len"] = None if r.min_len == 2**64 - 1 else r.max_len
+        d["min_len"] = None if min_len == 2**64 - 1 else min_len
+        d["max_len"] = None if min_len == 2**64 - 1 else max_len
     if q["mode"] == "store":
-        d["written"] = r.written
+        d["written"] = written
     return d
 
 
@@ -395,7 +438,8 @@ def last_stats() -> dict:
 
 def last_slices():
     """Per-slice records of the last enumeration as a numpy structured array
-    (elements, rows, t_begin, t_end; clocks in 100 MHz ticks)."""
+    (elements, rows, prefixes, t_begin, t_end, query, slice; clocks in 100 MHz
+    ticks)."""
     n = ctypes.c_uint32(0)
     _check(_lib.fz_last_slices(None, 0, ctypes.byref(n)), "fz_last_slices")
     buf = (fz_slice_info * max(n.value, 1))()
