@@ -775,6 +775,7 @@ double estimate_work(const FzPlan &P)
     estimate_counts(P, &rows, &pref, &el);
     if (P.prune)
         return P.w_skip * rows + (double)(P.w_row + P.w_chunk + P.w_el) * el;
+    if (P.pack) return P.w_row * rows + P.w_chunk * (pref / FZK_WAVE) + P.w_el * el;
     return P.w_row * rows + P.w_chunk * (pref / FZK_WAVE + rows) + P.w_el * el;
 }
 
@@ -1522,6 +1523,7 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices)
     for (uint32_t i = 0; i < k; ++i) {
         out[i].elements = tmp[i].elements;
         out[i].rows = tmp[i].rows;
+        out[i].prefixes = tmp[i].prefixes;
         out[i].t_begin = tmp[i].t_begin;
         out[i].t_end = tmp[i].t_end;
         out[i].query = c->last_batch ? items[i].q : 0;
