@@ -135,7 +135,7 @@ def percentile(v, p):
     return v[k]
 
 
-def measure_batch(fz, reps=3):
+def measure_batch(fz, reps=3, autotune=True):
     """The 4096-query mixed batch (count / histogram / predicate) as one
     fz_batch call; median of reps, every result checked against the stored
     counts."""
@@ -179,6 +179,10 @@ def measure_batch(fz, reps=3):
            "workload": "4096 queries: d in 3..8, generators in [5,1000], n log-uniform in "
                        "[1e3,1e6], |Z| <= 1e8, consumer count/hist/exists"}
     out["default"] = timed("default slices")
+    if not autotune:
+        out.update({k: out["default"][k] for k in ("ms", "queries_per_s", "factorizations_per_s",
+                                                    "prep_ms", "walk_ms")})
+        return out
     # the autotuner picks slices per wave and workgroups per CU on this batch
     tune = fz.autotune(qs, reps=1)
     out["autotune"] = {k: tune[k] for k in ("slices_per_wave", "workgroups_per_cu", "candidates")}
@@ -377,6 +381,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the batch with the default slices only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 1 GiB device to device 3 times (the "
                          "reference kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -547,7 +553,7 @@ def main():
         log("copy calibration done (3 x 1 GiB)")
     if not args.no_batch:
         log("batch (4096 queries) ...")
-        res["batch"] = measure_batch(fz)
+        res["batch"] = measure_batch(fz, autotune=not args.no_autotune)
     if not args.no_served:
         log("served stream (20000 queries) ...")
         res["served"] = measure_served(fz, torch)

@@ -382,6 +382,21 @@ void set_variant(FzPlan &P)
     P.cdv = 1;
 }
 
+// The packed walk's lanes step x by sx = D / gcd(g_{d-2}, D): only the x with
+// x g_{d-2} = R (mod D), D = gcd(A, B), can have an element (the
+// common-divisor skip of Sec. 3.2.4).  Counts, histograms and predicates of
+// the packed walk visit the same elements with fewer idle lanes.
+void set_lane_stride(FzPlan &P)
+{
+    const uint64_t D = P.D;
+    const uint64_t e2 = gcd64(P.G2, D);
+    uint64_t sx = D / e2;
+    if (sx >= (1u << 16)) sx = 1;
+    P.cd_sx = (uint32_t)sx;
+    P.cd_e2 = (uint32_t)e2;
+    P.cd_inv2 = sx > 1 ? modinv((P.G2 / e2) % sx, sx) : 0;
+}
+
 // Slice count, walker grid and walker variant of plan P on a device with
 // `cus` compute units (no allocation).
 void plan_launch(int cus, FzPlan &P, Launch &L)
@@ -419,6 +434,7 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
     }
     set_variant(P);
     P.pack = pack_rows(P);
+    if (P.pack) set_lane_stride(P);
     // trailing-index tables: rows of the block walk (d >= 4, no row skipping
     // or pair table), count and store
     P.trail = (g_trailing && !P.notab && !P.prune && !P.pair && !P.cdv && !P.pack && P.d >= 4 &&
@@ -882,6 +898,7 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
         P.pair = 0;
         // the batch walker walks every order-free consumer packed
         P.pack = P.mode != FZM_STORE ? 1 : 0;
+        if (P.pack) set_lane_stride(P);
         work[i] = estimate_work(P);
         est_total += work[i];
         maxm = std::max(maxm, P.d - 3);

@@ -127,8 +127,11 @@ __device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM
     // with an element
     const uint64_t lanes =
         P.pair ? PC[v] - (t * (uint64_t)P.G2 <= v ? PC[v - t * P.G2] : 0) : (uint64_t)t;
-    const uint64_t chunks = (lanes + FZK_WAVE - 1) / FZK_WAVE;
+    // (the packed walk shares chunks between rows: a lane prefix costs a
+    // 64th of one)
+    const uint64_t chunks = P.pack ? 0 : (lanes + FZK_WAVE - 1) / FZK_WAVE;
     uint64_t w = P.w_row + chunks * P.w_chunk;
+    if (P.pack) w += (lanes * P.w_chunk + FZK_WAVE - 1) / FZK_WAVE;
     const uint64_t we = el * P.w_el;
     return (P.w_el && we / P.w_el != el) ? ~0ull : sat_add(w, we);
 }
@@ -1155,6 +1158,9 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
         // lane's x from its remainder alone.
         if constexpr (PACK) {
             const uint32_t dl = M - 1;
+            // the lanes' x stride: the common-divisor skip of the last pair
+            // (Sec. 3.2.4), D = gcd(A, B) > 1
+            const uint32_t sxp = P.cd_sx;
             uint32_t gy = 0;
 #pragma unroll
             for (int k = 0; k < MAXM; ++k)
@@ -1187,13 +1193,25 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 const uint32_t nb = (uint32_t)__builtin_popcountll(__ballot(in));
                 const bool end_here = ueq && ay + nb - 1 == ey;
                 const uint32_t R = R0 - (uint32_t)off; // meaningful for lanes in
-                const int32_t x0 = lane == 0 ? xs : 0;
+                int32_t x0 = lane == 0 ? xs : 0;
                 const int32_t xl_row =
                     (end_here && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
                 bool has = in && xl_row >= x0;
+                if (sxp > 1 && has) {
+                    // only x with x G2 = R (mod D) can have an element: none
+                    // when e2 does not divide R, else every sxp-th x from
+                    // the first at or after x0
+                    const uint32_t r2 = R % P.D;
+                    const uint32_t xst =
+                        (uint32_t)((uint64_t)(r2 / P.cd_e2) * P.cd_inv2 % sxp);
+                    x0 += (int32_t)((xst + sxp - (uint32_t)x0 % sxp) % sxp);
+                    has = r2 % P.cd_e2 == 0 && xl_row >= x0;
+                }
                 if constexpr (PRUNE)
                     if (has) has = io.S[(uint64_t)M * P.stride + R] != 0;
-                const uint32_t np = has ? (uint32_t)(xl_row - x0 + 1) : 0u;
+                const uint32_t np =
+                    has ? (sxp > 1 ? (uint32_t)(xl_row - x0) / sxp : (uint32_t)(xl_row - x0)) + 1u
+                        : 0u;
                 lane_pref64 += np;
                 const uint64_t excl = wave_incl_scan64(np, lane) - np;
                 const uint64_t T = readlane64(excl + np, FZK_WAVE - 1);
@@ -1220,8 +1238,10 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     const bool active = p0 + lane < T;
                     const uint32_t Rj = (uint32_t)__shfl((int)R, (int)jl, FZK_WAVE);
                     const uint32_t ej = (uint32_t)__shfl((int)exlo, (int)jl, FZK_WAVE);
-                    // x = x0_j + (p - excl_j); the lane's remainder Rj - x G2 >= 0
-                    const uint32_t x = (jl == 0 ? (uint32_t)xs : 0u) + ((uint32_t)p0 + lane - ej);
+                    // x = x0_j + sxp (p - excl_j); the lane's remainder Rj - x G2 >= 0
+                    const uint32_t k = (uint32_t)p0 + lane - ej;
+                    const uint32_t x = sxp > 1 ? (uint32_t)__shfl(x0, (int)jl, FZK_WAVE) + sxp * k
+                                               : (jl == 0 ? (uint32_t)xs : 0u) + k;
                     const uint32_t Rc = Rj - x * P.G2;
                     const uint32_t Qv = fdiv(Rc, P.div_B);
                     const uint32_t Pv = Rc - Qv * P.B;

@@ -49,6 +49,12 @@ CASES = tiny_cases(41, 40) + [
     (3000, [13, 37, 38, 40, 41, 42]),
     (10000, [11, 13, 17, 23]),                            # the d = 4 query
     (300, [3, 5, 7, 11, 13, 17, 19]),                     # dense, long rows
+    # the last pair (two smallest) shares a divisor D that the third smallest
+    # does not: lanes step x by D (common-divisor skip)
+    (20000, [748, 647, 558, 525, 364, 26]),               # D = 26
+    (5000, [101, 77, 30, 20]),                            # D = 10
+    (3000, [97, 89, 45, 33, 22]),                         # D = 11
+    (500, [15, 12, 8]),                                   # d = 3, D = 4
 ]
 
 
@@ -86,7 +92,7 @@ def test_packed_walk_slices_inside_rows(fz, skip):
         fz.config_set("packed", 1)
         fz.config_set("skip_empty_rows", skip)
         fz.config_set("min_slice_work", 1)
-        for n, g in CASES[-8:]:
+        for n, g in CASES[-12:]:
             check_order_free(fz, n, g)
     finally:
         fz.config_set("packed", 0)
