@@ -213,6 +213,9 @@ typedef struct {
     uint64_t submitted, completed, launches;
     double mean_batch;         /* queries per launch */
     double p50_us, p99_us, max_us, mean_us; /* fz_submit to result ready */
+    double mean_phase1_us;     /* per launch: admission to the walk's launch
+                                  (tables, their totals read back, the cut) */
+    double mean_phase2_us;     /* per launch: the walk's launch to its last result */
 } fz_server_stats;
 
 int fz_server_create(const fz_server_cfg *cfg, fz_server **out); /* cfg may be NULL */
@@ -297,7 +300,9 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * histogram and predicate: the lane prefixes of up to 64 consecutive rows
  * of the deepest row level are walked end to end, 64 at a time; 0: for
  * sparse sets that skip empty rows, 1: always, 2: never; the batch walker
- * walks every order-free consumer packed).
+ * walks every order-free consumer packed), "batch_min_item_work" (the least
+ * modelled work of a batch's work item, so that a small batch is not cut
+ * into a chip's worth of tiny items; up to 2^30; 0: 2^20 units).
  * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */

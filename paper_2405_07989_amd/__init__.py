@@ -86,7 +86,8 @@ class fz_server_stats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("mean_batch", ctypes.c_double),
                 ("p50_us", ctypes.c_double), ("p99_us", ctypes.c_double),
-                ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double)]
+                ("max_us", ctypes.c_double), ("mean_us", ctypes.c_double),
+                ("mean_phase1_us", ctypes.c_double), ("mean_phase2_us", ctypes.c_double)]
 
 
 MODES = {"count": 0, "hist": 1, "exists": 2, "store": 3}

@@ -97,6 +97,7 @@ uint32_t g_host_threads = 0; // hybrid pool: host worker threads (0: off)
 uint32_t g_host_ppm = 0;     // their share of the work in millionths (0: kHostPpmPerThread each)
 uint32_t g_trailing = 0;     // 1: trailing-index tables (count and store of the block walk)
 uint32_t g_pack_mode = 0;    // packed walk of short rows: 0 by row length, 1 always, 2 never
+uint64_t g_batch_min_item = 0; // 0: kBatchMinItemWork
 
 bool worth_pruning(const FzPlan &P);
 uint32_t pack_rows(const FzPlan &P);
@@ -850,6 +851,8 @@ void BatchSlot::release()
 constexpr uint32_t kBatchRow = 880, kBatchRowSkipping = 2370, kBatchChunk = 300,
                    kBatchSkip = 62;
 constexpr uint32_t kBatchElem[4] = {35, 40, 40, 48}; // count, hist, exists, store
+// Least modelled work of a batch's work item (a 64-lane chunk is ~300 units).
+constexpr uint64_t kBatchMinItemWork = 1u << 20;
 // Skipping pays off only on sets with enough rows.
 constexpr double kPruneMinRows = 4096.0;
 
@@ -916,7 +919,8 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
     std::vector<uint32_t> &tabled = S.tabled;
     tabled.clear();
     uint64_t tab_words = 0, res_words = 0, bin_words = 0;
-    const double est_target = std::max(est_total / slots, 1.0);
+    const double est_target =
+        std::max(est_total / slots, (double)(g_batch_min_item ? g_batch_min_item : kBatchMinItemWork));
     for (uint32_t i = 0; i < nq; ++i) {
         FzBatchQuery &B = Q[i];
         FzPlan &P = B.plan;
@@ -1093,7 +1097,12 @@ int batch_launch_walk(BatchSlot &S)
     }
     for (uint32_t i = 0; i < nq; ++i)
         if (Q[i].plan.d) total += Q[i].sliced ? exact[i] : work[i];
-    const double target = std::max(total / slots, 1.0);
+    // (a small batch is not cut into a full chip's worth of tiny items: each
+    // item carries at least kBatchMinItemWork units, a few hundred
+    // microseconds of a wave -- its set-up, histogram flush and records cost
+    // tens of microseconds)
+    const double target =
+        std::max(total / slots, (double)(g_batch_min_item ? g_batch_min_item : kBatchMinItemWork));
     std::vector<uint32_t> order;
     uint32_t n_items = 0, n_bounds = 0;
     for (uint32_t i = 0; i < nq; ++i) {
@@ -1551,7 +1560,11 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices)
 
 int fz_config_set(const char *key, int64_t value)
 {
-    if (key == nullptr || value < 0 || value > (1 << 20)) return FZ_EINVAL;
+    if (key == nullptr || value < 0) return FZ_EINVAL;
+    // (every knob is a size or weight up to 2^20 but the batch's least item
+    // work, up to 2^30)
+    if (value > (std::strcmp(key, "batch_min_item_work") == 0 ? (1 << 30) : (1 << 20)))
+        return FZ_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     if (std::strcmp(key, "slices_per_wave") == 0) g_slices_per_wave = (uint32_t)value;
     else if (std::strcmp(key, "workgroups_per_cu") == 0) g_wg_per_cu = (uint32_t)value;
@@ -1570,6 +1583,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "host_share_ppm") == 0 && value <= 500000) g_host_ppm = (uint32_t)value;
     else if (std::strcmp(key, "trailing") == 0 && value <= 1) g_trailing = (uint32_t)value;
     else if (std::strcmp(key, "packed") == 0 && value <= 2) g_pack_mode = (uint32_t)value;
+    else if (std::strcmp(key, "batch_min_item_work") == 0) g_batch_min_item = (uint64_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

@@ -65,6 +65,7 @@ struct Slot {
     std::vector<fz_query> qs;
     std::vector<uint8_t> delivered;
     uint32_t left = 0;
+    Clock::time_point t_admit, t_walk; // launch of phase 1, of phase 2
 };
 
 // Device bytes a query may need in a slot: count and work tables (if it is
@@ -98,6 +99,18 @@ struct fz_server {
     std::unordered_map<uint64_t, Outcome> outcomes;
     std::vector<double> latency_us;
     uint64_t submitted = 0, completed = 0, launches = 0, launched_queries = 0;
+    // launch phases summed over finished launches: phase 1 (admission to
+    // the walk's launch: tables, totals read back, cut) and phase 2 (walk
+    // launch to the launch's last result)
+    double phase1_us = 0, phase2_us = 0;
+    uint64_t phased = 0;
+    void phases_done(const Slot &sl)
+    {
+        const Clock::time_point now = Clock::now();
+        phase1_us += std::chrono::duration<double, std::micro>(sl.t_walk - sl.t_admit).count();
+        phase2_us += std::chrono::duration<double, std::micro>(now - sl.t_walk).count();
+        ++phased;
+    }
 
     std::vector<Slot> slots;
     std::thread th;
@@ -143,6 +156,7 @@ void fz_server::run()
                         std::lock_guard<std::mutex> g(g_mu);
                         rc = batch_launch_walk(sl.b);
                     }
+                    sl.t_walk = Clock::now();
                     if (rc == FZ_OK && hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) {
                         (void)hipGetLastError();
                         rc = FZ_EDEVICE;
@@ -179,6 +193,7 @@ void fz_server::run()
                 delivered_any = true;
             }
             if (e == hipSuccess) {
+                phases_done(sl);
                 // a query the completed launch did not finish would be a bug
                 // of the walker: report it rather than wait for it
                 fz_result r{};
@@ -260,6 +275,7 @@ void fz_server::run()
             sl.delivered.assign(sl.reqs.size(), 0);
             sl.left = (uint32_t)sl.reqs.size();
             sl.busy = true;
+            sl.t_admit = sl.t_walk = Clock::now();
             ++launches;
             launched_queries += sl.reqs.size();
             lk.unlock();
@@ -411,9 +427,15 @@ int fz_server_stats_read(fz_server *s, fz_server_stats *out, int reset)
         for (double x : v) sum += x;
         st.mean_us = sum / v.size();
     }
+    if (s->phased) {
+        st.mean_phase1_us = s->phase1_us / s->phased;
+        st.mean_phase2_us = s->phase2_us / s->phased;
+    }
     if (reset) {
         s->latency_us.clear();
         s->submitted = s->completed = s->launches = s->launched_queries = 0;
+        s->phase1_us = s->phase2_us = 0;
+        s->phased = 0;
     }
     *out = st;
     return FZ_OK;
