@@ -436,6 +436,8 @@ def main():
     value = (N + M) / (elapsed / args.steps)
     valu_probe = fz.probe_int_valu()  # after the timed steps
     log(f"int32 add probe: {valu_probe['lane_ops_per_s'] / 1e12:.2f} Tops/s")
+    write_probe = fz.probe_hbm_write(M * 4 * len(g))  # as many bytes as the store writes
+    log(f"HBM write probe: {write_probe['bytes_per_s'] / 1e9:.0f} GB/s")
     kt = {k: fz.profile_read(k) for k in ["dp", "restab", "slices", "enum.count", "enum.store",
                                           "finalize"]}
     cnt_ms, cnt_n = kt["enum.count"]
@@ -487,6 +489,9 @@ def main():
             "frac": store_bw / PEAK_HBM_BYTES,
             "traffic": None,
             "avg_launch_ms": avg_store_s * 1e3,
+            # the device's own sustained write rate (fz_probe_hbm_write,
+            # 16-byte stores, same byte count)
+            "measured_write_peak": write_probe["bytes_per_s"] / 1e9,
         },
         "count_factorizations_per_s": N / avg_count_s,
         "store_factorizations_per_s": M / avg_store_s,

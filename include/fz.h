@@ -349,6 +349,15 @@ const char *fz_last_error(void);
  * rate, FZ_EDEVICE / FZ_ENOMEM on HIP errors. */
 int fz_probe_int_valu(double *lane_ops_per_s, double *ms);
 
+/* Diagnostic: the current device's sustained HBM write rate in bytes per
+ * second (*bytes_per_s): a kernel writes a fresh device buffer of `bytes`
+ * (at least 1 MiB; rounded down to 16 B) with 16-byte stores in a
+ * grid-stride loop, reading nothing; *ms (may be NULL) is its best time of
+ * three.  The ceiling that the store walker's write rate is compared with.
+ * The buffer is allocated and freed by the call.  FZ_EINVAL for a NULL rate
+ * or fewer bytes, FZ_ENOMEM / FZ_EDEVICE on HIP errors. */
+int fz_probe_hbm_write(uint64_t bytes, double *bytes_per_s, double *ms);
+
 /* Static description of a status code. */
 const char *fz_strerror(int status);
 

@@ -125,6 +125,8 @@ _SIGS = {
     "fz_wait": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(fz_result)]),
     "fz_server_stats_read": (ctypes.c_int, [_vp, ctypes.POINTER(fz_server_stats), ctypes.c_int]),
     "fz_server_destroy": (ctypes.c_int, [_vp]),
+    "fz_probe_hbm_write": (ctypes.c_int, [ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
     "fz_probe_int_valu": (ctypes.c_int, [ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double)]),
 }
@@ -473,6 +475,14 @@ def probe_int_valu() -> dict:
     rate, ms = ctypes.c_double(0), ctypes.c_double(0)
     _check(_lib.fz_probe_int_valu(ctypes.byref(rate), ctypes.byref(ms)), "fz_probe_int_valu")
     return {"lane_ops_per_s": rate.value, "ms": ms.value}
+
+
+def probe_hbm_write(nbytes: int = 12 * 10**9) -> dict:
+    """fz_probe_hbm_write: the device's sustained HBM write rate."""
+    rate, ms = ctypes.c_double(0), ctypes.c_double(0)
+    _check(_lib.fz_probe_hbm_write(nbytes, ctypes.byref(rate), ctypes.byref(ms)),
+           "fz_probe_hbm_write")
+    return {"bytes_per_s": rate.value, "ms": ms.value}
 
 
 def strerror(status: int) -> str:
