@@ -302,7 +302,13 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * sparse sets that skip empty rows, 1: always, 2: never; the batch walker
  * walks every order-free consumer packed), "batch_min_item_work" (the least
  * modelled work of a batch's work item, so that a small batch is not cut
- * into a chip's worth of tiny items; up to 2^30; 0: 2^20 units).
+ * into a chip's worth of tiny items; up to 2^30; 0: 2^20 units),
+ * "wave_bins32" (single-query histograms of up to ~680 bins: 1, the default:
+ * each wave adds its runs to 32-bit bins of its own in LDS, folded into the
+ * workgroup's 64-bit bins before they could overflow; 0: all waves add to the
+ * workgroup's 64-bit bins), "wave_bins32_limit" (the elements a wave's
+ * 32-bit bins may hold before they are folded, at most 2^20 here; 0: 2^31;
+ * small values exercise the folding).
  * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */

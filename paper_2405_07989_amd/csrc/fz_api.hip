@@ -37,6 +37,8 @@ constexpr uint32_t kMaxHostThreads = 64;
 // Trailing-index tables of a store: at most 2 GiB of triples.
 constexpr uint64_t kTrailBytes = 2ull << 30;
 constexpr size_t kLdsHistBudget = 64 * 1024;
+// ... and for the workgroup's set with a 32-bit set per wave beside it.
+constexpr size_t kLdsHist32Budget = 16 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
 // per-wave LDS histogram in batches, 8 KB per wave: 1024 64-bit bins, or
 // 2048 32-bit bins for a histogram that needs more
@@ -98,6 +100,8 @@ uint32_t g_host_ppm = 0;     // their share of the work in millionths (0: kHostP
 uint32_t g_trailing = 0;     // 1: trailing-index tables (count and store of the block walk)
 uint32_t g_pack_mode = 0;    // packed walk of short rows: 0 by row length, 1 always, 2 never
 uint64_t g_batch_min_item = 0; // 0: kBatchMinItemWork
+uint32_t g_hist32 = 1;         // single-query histograms: 32-bit LDS bins per wave when they fit
+uint64_t g_hist32_limit = 0;   // their fold threshold in elements (0: 2^31)
 
 bool worth_pruning(const FzPlan &P);
 uint32_t pack_rows(const FzPlan &P);
@@ -425,6 +429,13 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
         P.prune = P.pair = 0;
         P.min_slice_work = 0; // no work table: always the full slice count
     }
+    // a 32-bit set of bins per wave beside the workgroup's 64-bit set, when
+    // both fit in kLdsHist32Budget (the waves' flushes are sized by slice
+    // ranks, so not without tables)
+    if (P.hist_in_lds && !P.notab && g_hist32 &&
+        (size_t)((P.nbins + 2) & ~1u) * (8 + 4 * (FZK_WG / FZK_WAVE)) <= kLdsHist32Budget)
+        P.hist_in_lds = 2;
+    P.hist32_limit = g_hist32_limit ? g_hist32_limit : (1ull << 31);
     // hybrid pool (order-free consumers with tables): host threads take the
     // last slices of the work
     P.host_slices = 0;
@@ -1584,6 +1595,8 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "trailing") == 0 && value <= 1) g_trailing = (uint32_t)value;
     else if (std::strcmp(key, "packed") == 0 && value <= 2) g_pack_mode = (uint32_t)value;
     else if (std::strcmp(key, "batch_min_item_work") == 0) g_batch_min_item = (uint64_t)value;
+    else if (std::strcmp(key, "wave_bins32") == 0 && value <= 1) g_hist32 = (uint32_t)value;
+    else if (std::strcmp(key, "wave_bins32_limit") == 0) g_hist32_limit = (uint64_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

@@ -51,7 +51,9 @@ struct FzPlan {
     uint32_t w_el;       // ... of one element
     uint32_t restab_in_lds;
     uint32_t nbins;      // histogram bins (n / min g + 1)
-    uint32_t hist_in_lds; // histogram bins: 0 global, 1 per-wave LDS 64-bit, 2 per-wave LDS 32-bit
+    uint32_t hist_in_lds; // histogram bins: 0 global; a batch: 1 per-wave LDS 64-bit, 2 per-wave
+                          // LDS 32-bit; a single query: 1 the workgroup's LDS 64-bit set, 2 that
+                          // set and a 32-bit set per wave
     uint32_t prune;      // skip rows whose subtree is empty (sparse sets; needs S)
     uint32_t pair;       // walk only the pair remainders the last pair represents (pair table)
     uint32_t w_skip;     // slice-cut weight of a skipped (empty) row
@@ -91,6 +93,11 @@ struct FzPlan {
     // d >= 4): the lane prefixes of up to 64 consecutive rows of the deepest
     // row level fill the chunks end to end.
     uint32_t pack;
+    // Single-query histograms with a 32-bit set of bins per wave: a wave
+    // folds its set into the workgroup's before it holds this many elements
+    // (at most 2^31), and walks a slice of at least this many elements into
+    // the workgroup's set directly.
+    uint64_t hist32_limit;
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag

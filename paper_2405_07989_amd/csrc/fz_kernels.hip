@@ -562,7 +562,12 @@ __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint
         const uint32_t hi0 = lo + cnt * mag;
         const uint32_t hi = (mag != 0 && hi0 < P.nbins) ? hi0 : P.nbins;
         const uint64_t inc = mag != 0 ? 1ull : (uint64_t)cnt;
-        if (P.hist_in_lds) { // the workgroup's bins
+        if (P.hist_in_lds == 2 && io.wbins32) { // the wave's own 32-bit bins
+            __hip_atomic_fetch_add(&io.wbins32[lo], (uint32_t)inc, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&io.wbins32[hi], 0xFFFFFFFFu, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else if (P.hist_in_lds) { // the workgroup's bins
             __hip_atomic_fetch_add(&io.wbins[lo], inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_add(&io.wbins[hi], ~0ull, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1485,12 +1490,37 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.TO = Bf.TO;
     io.TT = Bf.TT;
     io.trail_m = P.trail ? Bf.ctl->trail_m : 0;
+    // Histogram bins in LDS: one 64-bit set for the workgroup (hist_in_lds
+    // 1), or (2) besides it a 32-bit set per wave, which takes the wave's
+    // runs and is added into the workgroup's set before it could overflow:
+    // every difference entry of a wave's set is bounded by the elements the
+    // wave added since its last flush, kept below P.hist32_limit <= 2^31 (a
+    // slice's exact element count comes from its ranks).  Private 32-bit sets halve the
+    // atomics' LDS traffic and keep the waves off each other's bins.
+    const uint32_t stride32 = (P.nbins + 2) & ~1u; // nbins + 1 words, even
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) { // one set of bins for the workgroup's waves
             io.wbins = (uint64_t *)scratch;
             for (uint32_t i = threadIdx.x; i <= P.nbins; i += blockDim.x) io.wbins[i] = 0;
+            if (P.hist_in_lds == 2) {
+                io.wbins32 = (uint32_t *)(io.wbins + stride32) + wave * stride32;
+                for (uint32_t i = lane; i <= P.nbins; i += FZK_WAVE) io.wbins32[i] = 0;
+            }
         }
     }
+    // a wave adds its 32-bit set (sign-extended) into the workgroup's, then
+    // clears it
+    auto flush32 = [&]() {
+        for (uint32_t i = lane; i <= P.nbins; i += FZK_WAVE) {
+            const int32_t v = (int32_t)io.wbins32[i];
+            if (v != 0) {
+                __hip_atomic_fetch_add(&io.wbins[i], (uint64_t)(int64_t)v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                io.wbins32[i] = 0;
+            }
+        }
+    };
+    uint64_t wave_el = 0; // elements in the wave's 32-bit set
     // store scratch per wave: scan (64 x u64), t0, ad0 and x (64 x u32
     // each), then the staging block of 64 rows x d_user words
     const uint32_t store_words = 5 * FZK_WAVE + FZK_WAVE * P.d_user;
@@ -1518,10 +1548,22 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         }
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
+        WalkIO ios = io;
+        if constexpr (MODE == FZM_HIST) {
+            if (P.hist_in_lds == 2) {
+                const uint64_t n_s = Bf.base[s + 1] - Bf.base[s];
+                if (wave_el + n_s >= P.hist32_limit) {
+                    flush32();
+                    wave_el = 0;
+                }
+                if (n_s >= P.hist32_limit) ios.wbins32 = nullptr; // this slice: 64-bit bins
+                else wave_el += n_s;
+            }
+        }
         const WalkOut o =
             walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2 || VAR == 5), (VAR == 2), true,
                        (VAR == 3), (VAR == 4 || VAR == 5)>(
-                P, M, b0, b0 + NP, Bf.base[s], io, lane);
+                P, M, b0, b0 + NP, Bf.base[s], ios, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -1534,6 +1576,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     }
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) { // every wave has left the loop: the bins are whole
+            if (P.hist_in_lds == 2) flush32();
             __syncthreads();
             uint64_t *grow = Bf.hist_rows + (uint64_t)blockIdx.x * P.nbins;
             for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = io.wbins[i];
@@ -2288,6 +2331,9 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
     const uint32_t waves = FZK_WG / FZK_WAVE;
     size_t bytes = p.restab_in_lds ? (size_t)2 * ((2 * p.B + 1) & ~1u) * sizeof(uint32_t) : 0;
     if (p.mode == FZM_HIST && p.hist_in_lds) bytes += ((size_t)p.nbins + 1) * sizeof(uint64_t);
+    if (p.mode == FZM_HIST && p.hist_in_lds == 2) // the 64-bit set padded to even words, then 32-bit sets
+        bytes += ((size_t)((p.nbins + 2) & ~1u) - (p.nbins + 1)) * sizeof(uint64_t) +
+                 (size_t)waves * ((p.nbins + 2) & ~1u) * sizeof(uint32_t);
     if (p.mode == FZM_STORE)
         bytes += (size_t)waves * (5 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
     return bytes;
