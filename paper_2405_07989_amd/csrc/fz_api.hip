@@ -1138,8 +1138,10 @@ int batch_launch_walk(BatchSlot &S)
         n_bounds += B2.n_slices + 1;
         order.push_back(i);
     }
+    const bool small_first = S.small_first;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) {
-        if (Q[a].sliced != Q[b].sliced) return Q[a].sliced > Q[b].sliced;
+        if (Q[a].sliced != Q[b].sliced) return (Q[a].sliced > Q[b].sliced) != small_first;
+        if (small_first && !Q[a].sliced) return work[a] < work[b];
         return work[a] / Q[a].n_slices > work[b] / Q[b].n_slices;
     });
     for (uint32_t i : order) {

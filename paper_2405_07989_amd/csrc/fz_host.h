@@ -57,6 +57,11 @@ struct BatchSlot {
     uint32_t cus = 0, wgcu = 0, maxm = 0, max_du = 0, lds_bins = 0, bstride = 1;
     bool profile = false;
     bool walk_pending = false;      // phase 1 queued, phase 2 not yet
+    // item order: false (fz_batch) the largest items first, for the shortest
+    // whole batch; true (the server) the uncut queries first, so that small
+    // queries finish at the start of the walk instead of after the large
+    // ones' items have been taken
+    bool small_first = false;
     void release();
 };
 

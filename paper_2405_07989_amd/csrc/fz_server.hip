@@ -347,6 +347,7 @@ int fz_server_create(const fz_server_cfg *cfg, fz_server **out)
     if (c.max_store_tuples) s->store_cap = c.max_store_tuples;
     s->slots.resize(s->inflight);
     for (Slot &sl : s->slots) {
+        sl.b.small_first = true; // latency: a launch's small queries are walked first
         e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming);
         if (e != hipSuccess) {
