@@ -33,6 +33,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 FZ_OK, FZ_TRUNCATED = 0, 1
 FZ_EINVAL, FZ_EOVERFLOW, FZ_ENOMEM, FZ_EDEVICE, FZ_E2BIG, FZ_EINTERNAL = -1, -2, -3, -4, -5, -6
 FZ_MAX_D = 16
+FZ_MAX_LAST_GEN = 1 << 24
 
 
 class FzError(RuntimeError):
@@ -302,17 +303,26 @@ def _marshal(queries):
         q = queries[i]
         nb = q.get("nbins")
         if not nb:
-            gp = ctypes.cast(gbase + 4 * int(goff[i]), _u32p)
-            nb = max(int(_lib.fz_length_bins(q["n"], gp, int(ds[i]))), 1)
+            g = q["g"]
+            n = q["n"]
+            # fz_length_bins' value, n // min g + 1, for a query plainly
+            # inside the limits; the library decides every other one
+            if 1 <= len(g) <= FZ_MAX_D and 0 <= n < 2**30 and min(g) >= 1 and \
+                    n + 2 * max(max(g), n + 1 if len(g) == 1 else 0) < 2**31 and \
+                    g[-1] <= FZ_MAX_LAST_GEN:
+                nb = n // min(g) + 1
+            else:
+                gp = ctypes.cast(gbase + 4 * int(goff[i]), _u32p)
+                nb = max(int(_lib.fz_length_bins(n, gp, int(ds[i]))), 1)
         nbs.append(nb)
     bins_all = np.zeros(sum(nbs), dtype=np.uint64)
-    off = 0
-    for i, nb in zip(hist, nbs):
-        bins = bins_all[off:off + nb]
-        queries[i]["_bins"] = bins
-        qa["bins"][i] = bins.ctypes.data
-        qa["nbins"][i] = nb
-        off += nb
+    if hist:
+        boff = np.zeros(len(hist), dtype=np.uint64)
+        np.cumsum(np.asarray(nbs[:-1], dtype=np.uint64), out=boff[1:])
+        qa["bins"][hist] = bins_all.ctypes.data + 8 * boff
+        qa["nbins"][hist] = nbs
+        for i, o, nb in zip(hist, boff.tolist(), nbs):
+            queries[i]["_bins"] = bins_all[o:o + nb]
     for i, q in enumerate(queries):
         if q["mode"] != "store":
             continue

@@ -549,7 +549,7 @@ struct WalkOut {
 // are two's complement: 64-bit bins, or 32-bit ones in a batch, where a bin
 // moves by at most the elements of one work item (< 2^30, checked on the
 // host) and is flushed, sign-extended, after every item.
-template <bool FIXED>
+template <bool FIXED, bool H32 = false>
 __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint32_t len0,
                                          uint32_t cnt, int32_t step)
 {
@@ -562,7 +562,7 @@ __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint
         const uint32_t hi0 = lo + cnt * mag;
         const uint32_t hi = (mag != 0 && hi0 < P.nbins) ? hi0 : P.nbins;
         const uint64_t inc = mag != 0 ? 1ull : (uint64_t)cnt;
-        if (P.hist_in_lds == 2 && io.wbins32) { // the wave's own 32-bit bins
+        if (H32 && io.wbins32) { // the wave's own 32-bit bins
             __hip_atomic_fetch_add(&io.wbins32[lo], (uint32_t)inc, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_fetch_add(&io.wbins32[hi], 0xFFFFFFFFu, __ATOMIC_RELAXED,
@@ -709,7 +709,7 @@ __device__ __forceinline__ void count_steps(uint32_t &cnt, int32_t &ad, int32_t 
 // walked 64 at a time, so that a chunk is not one row's few prefixes.  (With
 // no row level, M = 0, the one row is walked alone.)
 template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED, bool CDV = false,
-          bool PACK = false>
+          bool PACK = false, bool H32 = false>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                                               const uint32_t *b0, const uint32_t *b1,
                                               uint64_t rank, const WalkIO &io, uint32_t lane)
@@ -831,7 +831,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 lane_el += cnt;
                 if (cnt) {
                     const uint32_t len0 = plen + xl + t0 + (uint32_t)ad0;
-                    hist_run<FIXED>(P, io, len0, cnt, (int32_t)len_step);
+                    hist_run<FIXED, H32>(P, io, len0, cnt, (int32_t)len_step);
                 }
             } else if constexpr (MODE == FZM_EXISTS) {
                 // each element's length is compared with the target; the
@@ -1455,11 +1455,15 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
 // Single query.  Persistent workgroups of four waves; each wave takes slices
 // from an atomic cursor.
 // LDS: [residue table, 2B int2, when it fits][per-wave consumer scratch].
-// VAR: 0 plain, 1 skipping empty subtrees, 2 also walking only the pair
-// remainders the last pair represents.
-template <int M, int MODE, bool TLDS, int VAR>
+// VAR (low three bits): 0 plain, 1 skipping empty subtrees, 2 also walking
+// only the pair remainders the last pair represents, 3 the variant walk, 4
+// and 5 the packed walk without and with skipping; bit 3 (histograms): a
+// 32-bit set of LDS bins per wave beside the workgroup's.
+template <int M, int MODE, bool TLDS, int VARH>
 __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
 {
+    constexpr int VAR = VARH & 7;
+    constexpr bool H32 = MODE == FZM_HIST && (VARH & 8) != 0;
     extern __shared__ __align__(16) uint32_t lds[];
     constexpr uint32_t NP = M + 1;
     const uint32_t lane = __lane_id();
@@ -1502,7 +1506,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         if (P.hist_in_lds) { // one set of bins for the workgroup's waves
             io.wbins = (uint64_t *)scratch;
             for (uint32_t i = threadIdx.x; i <= P.nbins; i += blockDim.x) io.wbins[i] = 0;
-            if (P.hist_in_lds == 2) {
+            if (H32) {
                 io.wbins32 = (uint32_t *)(io.wbins + stride32) + wave * stride32;
                 for (uint32_t i = lane; i <= P.nbins; i += FZK_WAVE) io.wbins32[i] = 0;
             }
@@ -1549,8 +1553,8 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         const uint64_t t_begin = wall_clock64();
         const uint32_t *b0 = Bf.bounds + (uint64_t)s * NP;
         WalkIO ios = io;
-        if constexpr (MODE == FZM_HIST) {
-            if (P.hist_in_lds == 2) {
+        if constexpr (H32) {
+            {
                 const uint64_t n_s = Bf.base[s + 1] - Bf.base[s];
                 if (wave_el + n_s >= P.hist32_limit) {
                     flush32();
@@ -1562,8 +1566,8 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
         }
         const WalkOut o =
             walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2 || VAR == 5), (VAR == 2), true,
-                       (VAR == 3), (VAR == 4 || VAR == 5)>(
-                P, M, b0, b0 + NP, Bf.base[s], ios, lane);
+                       (VAR == 3), (VAR == 4 || VAR == 5), H32>(
+                P, M, b0, b0 + NP, Bf.base[s], H32 ? ios : io, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -1576,7 +1580,7 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     }
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) { // every wave has left the loop: the bins are whole
-            if (P.hist_in_lds == 2) flush32();
+            if constexpr (H32) flush32();
             __syncthreads();
             uint64_t *grow = Bf.hist_rows + (uint64_t)blockIdx.x * P.nbins;
             for (uint32_t i = threadIdx.x; i < P.nbins; i += blockDim.x) grow[i] = io.wbins[i];
@@ -2349,8 +2353,12 @@ static void launch_enum_mt(const FzPlan &p, const FzBufs &b, uint32_t nwg, hipSt
                            s, p, b);
         break;
     case FZM_HIST:
-        hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
-                           s, p, b);
+        if (p.hist_in_lds == 2)
+            hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS, VAR | 8>), dim3(nwg), dim3(FZK_WG),
+                               lds, s, p, b);
+        else
+            hipLaunchKernelGGL((fz_enum_kernel<M, FZM_HIST, TLDS, VAR>), dim3(nwg), dim3(FZK_WG),
+                               lds, s, p, b);
         break;
     case FZM_EXISTS:
         hipLaunchKernelGGL((fz_enum_kernel<M, FZM_EXISTS, TLDS, VAR>), dim3(nwg), dim3(FZK_WG), lds,
