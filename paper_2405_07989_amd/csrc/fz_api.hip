@@ -862,6 +862,11 @@ void BatchSlot::release()
 constexpr uint32_t kBatchRow = 880, kBatchRowSkipping = 2370, kBatchChunk = 300,
                    kBatchSkip = 62;
 constexpr uint32_t kBatchElem[4] = {35, 40, 40, 48}; // count, hist, exists, store
+// A batch table row of more entries than this is shared by several
+// workgroups (one per this many entries, at most one per chain).
+constexpr uint32_t kDpGroupEntries = 1u << 16;
+// ... when at most this many queries of a batch have such rows.
+constexpr uint32_t kDpMaxSharedQueries = 128;
 // Least modelled work of a batch's work item (a 64-lane chunk is ~300 units).
 constexpr uint64_t kBatchMinItemWork = 1u << 20;
 // Skipping pays off only on sets with enough rows.
@@ -960,13 +965,59 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
         B.out = qs[i].d_out;
     }
     const uint32_t n_tab = (uint32_t)tabled.size();
+    // Tables: one workgroup builds all rows of a query (one launch for all
+    // of them) -- but when few queries have large rows (more than
+    // kDpGroupEntries entries), a workgroup each would leave most of the
+    // chip idle: those are built pass by pass (their 2d - 3 row computations
+    // in order, a launch each), every row shared by up to one workgroup per
+    // kDpGroupEntries entries (by chains; C row M by ranges).  With many
+    // large queries the chip is full anyway, and one workgroup per query
+    // overlaps the queries' rows better than passes, which wait for their
+    // slowest row (4096-query batch: 6.4 ms against 20 ms).
+    std::vector<uint32_t> &pjobs = S.pass_jobs;
+    std::vector<uint32_t> &poff = S.pass_off;
+    std::vector<uint32_t> &small = S.small_ids;
+    pjobs.clear();
+    poff.assign(1, 0);
+    small.clear();
+    uint32_t n_pass = 0, n_large = 0;
+    for (uint32_t i : tabled) n_large += Q[i].plan.stride > kDpGroupEntries ? 1 : 0;
+    const bool by_pass = n_large > 0 && n_large <= kDpMaxSharedQueries;
+    for (uint32_t i : tabled) {
+        if (by_pass && Q[i].plan.stride > kDpGroupEntries)
+            n_pass = std::max(n_pass, 2 * Q[i].plan.d - 3);
+        else small.push_back(i);
+    }
+    for (uint32_t p = 0; p < n_pass; ++p) {
+        for (uint32_t i : tabled) {
+            const FzPlan &P = Q[i].plan;
+            if (!by_pass || P.stride <= kDpGroupEntries || p >= 2 * P.d - 3) continue;
+            const uint32_t parts = (uint32_t)((P.stride + kDpGroupEntries - 1) / kDpGroupEntries);
+            uint32_t G = parts;
+            if (p + 1 != P.d) { // a chain scan: row k of S or C, chains g_k
+                const uint32_t k = p + 2 <= P.d ? P.d - 2 - p : P.d - 4 - (p - P.d);
+                G = std::min(parts, std::min(P.g[k], P.stride));
+            }
+            G = std::max(G, 1u);
+            for (uint32_t w = 0; w < G; ++w) {
+                pjobs.push_back(i);
+                pjobs.push_back(w);
+                pjobs.push_back(G);
+            }
+        }
+        poff.push_back((uint32_t)(pjobs.size() / 3));
+    }
     auto up = [](size_t o) { return (o + 63) & ~(size_t)63; };
     const size_t o_q = 0;
     const size_t o_ids = up(o_q + (size_t)nq * sizeof(FzBatchQuery));
-    const size_t meta1 = up(o_ids + (size_t)n_tab * 4);
+    const size_t o_small = up(o_ids + (size_t)n_tab * 4);
+    const size_t o_pj = up(o_small + small.size() * 4);
+    const size_t meta1 = up(o_pj + pjobs.size() * 4);
     FZ_TRY(ensure_pinned((void **)&S.h_meta, &S.h_meta_cap, meta1));
     std::memcpy(S.h_meta + o_q, Q.data(), (size_t)nq * sizeof(FzBatchQuery));
     if (n_tab) std::memcpy(S.h_meta + o_ids, tabled.data(), (size_t)n_tab * 4);
+    if (!small.empty()) std::memcpy(S.h_meta + o_small, small.data(), small.size() * 4);
+    if (!pjobs.empty()) std::memcpy(S.h_meta + o_pj, pjobs.data(), pjobs.size() * 4);
     if (S.h_cap < nq) {
         size_t c1 = 0, c2 = 0;
         if (S.h_res) (void)hipHostFree(S.h_res);
@@ -1016,8 +1067,15 @@ int batch_launch_tables(BatchSlot &S, int cus, uint32_t spw, uint32_t wgcu, cons
     if (!any_valid) return FZ_OK; // every query was rejected on the host: nothing to walk
     FZ_TRY(hipMemcpyAsync(meta, S.h_meta, meta1, hipMemcpyHostToDevice, st));
     const uint32_t *ids = (const uint32_t *)(meta + o_ids);
-    if (profile) FZ_LAUNCH("batch.tables", st, fzk_launch_batch_tables(B, n_tab, ids, st));
-    else FZ_TRY(fzk_launch_batch_tables(B, n_tab, ids, st));
+    const uint32_t *sids = (const uint32_t *)(meta + o_small);
+    const uint32_t *pj = (const uint32_t *)(meta + o_pj);
+    const uint32_t n_small = (uint32_t)small.size();
+    if (profile)
+        FZ_LAUNCH("batch.tables", st,
+                  fzk_launch_batch_tables(B, n_tab, ids, n_small, sids, pj, poff.data(), n_pass,
+                                          st));
+    else
+        FZ_TRY(fzk_launch_batch_tables(B, n_tab, ids, n_small, sids, pj, poff.data(), n_pass, st));
     if (n_tab)
         FZ_TRY(hipMemcpyAsync(S.h_totals, S.totals.p, (size_t)n_tab * 16, hipMemcpyDeviceToHost,
                               st));

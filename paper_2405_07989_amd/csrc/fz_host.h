@@ -49,6 +49,8 @@ struct BatchSlot {
     // state kept between the two launch phases
     std::vector<double> work;
     std::vector<uint32_t> tabled;
+    std::vector<uint32_t> pass_jobs, pass_off; // table jobs pass by pass (host copies)
+    std::vector<uint32_t> small_ids;           // queries whose tables one workgroup builds
     FzBatchBufs B{};
     hipStream_t stream = nullptr;
     hipEvent_t tables_ev = nullptr; // recorded after the tables and their totals

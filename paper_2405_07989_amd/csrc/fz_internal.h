@@ -224,8 +224,16 @@ size_t fzk_enum_lds_bytes(const FzPlan &p);
 // batch: zeroing, count / work tables (and their totals) and residue tables;
 // then, once the host has cut the queries, slice bounds; then the persistent
 // walker, which also finishes each query
+// Tables of a batch: one workgroup builds all rows of each of the n_small
+// queries small_ids (device array); then pass p = 0 .. n_pass-1 launches the
+// jobs (query, group, groups) pass_jobs[3 pass_off[p] ..) (device array;
+// pass_off on the host, n_pass + 1 entries): one row computation of each
+// larger query, its rows shared by several workgroups; then the totals of
+// all n_tabled queries tabled_ids.
 hipError_t fzk_launch_batch_tables(const FzBatchBufs &b, uint32_t n_tabled,
-                                   const uint32_t *tabled_ids, hipStream_t s);
+                                   const uint32_t *tabled_ids, uint32_t n_small,
+                                   const uint32_t *small_ids, const uint32_t *pass_jobs,
+                                   const uint32_t *pass_off, uint32_t n_pass, hipStream_t s);
 hipError_t fzk_launch_batch_slices(const FzBatchBufs &b, hipStream_t s);
 hipError_t fzk_launch_batch_walk(const FzBatchBufs &b, uint32_t maxm, uint32_t nwg,
                                  uint32_t lds_bins, uint32_t max_du, hipStream_t s);

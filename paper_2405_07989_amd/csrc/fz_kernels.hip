@@ -140,20 +140,25 @@ __device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM
 // below(v), written to row[v]; in place is allowed (row[v] is written only
 // by the thread that read below(v)).  SAT: saturating adds (count tables);
 // else wrapping adds (the histogram's difference array, whose entries may be
-// negative in two's complement).
+// negative in two's complement).  The workgroup takes the chains c = c0,
+// c0 + cstep, ... (all of them by default): chains are independent, so
+// several workgroups can share a row.
 template <bool SAT, class Below>
-__device__ void chain_scan(uint64_t *row, uint32_t len, uint32_t gk, Below below, uint64_t *part)
+__device__ void chain_scan(uint64_t *row, uint32_t len, uint32_t gk, Below below, uint64_t *part,
+                           uint32_t c0 = 0, uint32_t cstep = 1)
 {
     const auto add = [](uint64_t a, uint64_t b) { return SAT ? sat_add(a, b) : a + b; };
     const uint32_t T = blockDim.x, tid = threadIdx.x;
     const uint32_t rows = (len - 1) / gk + 1;
-    const uint32_t cols = gk < len ? gk : len;
+    const uint32_t all = gk < len ? gk : len;
+    const uint32_t cols = all > c0 ? (all - c0 + cstep - 1) / cstep : 0; // this group's chains
+    if (cols == 0) return;
     const uint32_t nb = cols >= T ? 1 : T / cols;
     const uint32_t rpb = (rows + nb - 1) / nb;
     const uint32_t units = cols * nb;
     if (nb > 1) {
         for (uint32_t u = tid; u < units; u += T) {
-            const uint32_t c = u % cols, b = u / cols;
+            const uint32_t c = c0 + (u % cols) * cstep, b = u / cols;
             const uint32_t i1 = min(rows, (b + 1) * rpb);
             uint64_t s = 0;
             // independent loads first, then the dependent sum
@@ -181,7 +186,7 @@ __device__ void chain_scan(uint64_t *row, uint32_t len, uint32_t gk, Below below
         __syncthreads();
     }
     for (uint32_t u = tid; u < units; u += T) {
-        const uint32_t c = u % cols, b = u / cols;
+        const uint32_t c = c0 + (u % cols) * cstep, b = u / cols;
         const uint32_t i1 = min(rows, (b + 1) * rpb);
         uint64_t run = nb > 1 ? part[u] : 0;
         for (uint32_t i = b * rpb; i < i1; i += 8) {
@@ -1940,6 +1945,48 @@ __global__ void __launch_bounds__(1024) fz_batch_dp_kernel(FzBatchBufs B, const 
     dp_query<false>(P, B.tables + Q.s_off, B.tables + Q.c_off, part, nullptr, nullptr, nullptr);
 }
 
+// The same tables one row computation at a time for every query (pass p of a
+// query: S rows d-2 .. 0, then C row M from the row work, then C rows M-1 ..
+// 0), a row shared by G workgroups: job (q, w, G) takes the chains c = w
+// mod G of the row, or the w-th G-th of C row M.  A large query's rows then
+// use many compute units instead of one.
+__global__ void __launch_bounds__(1024) fz_batch_dp_pass_kernel(FzBatchBufs B, const uint32_t *jobs,
+                                                                 uint32_t p)
+{
+    __shared__ uint64_t part[1024];
+    const uint32_t q = jobs[3 * blockIdx.x], w = jobs[3 * blockIdx.x + 1],
+                   G = jobs[3 * blockIdx.x + 2];
+    const FzBatchQuery &Q = B.queries[q];
+    const FzPlan P = Q.plan; // P.pair is 0: batches walk without the pair table
+    uint64_t *S = B.tables + Q.s_off, *C = B.tables + Q.c_off;
+    const uint32_t d = P.d, M = d - 3;
+    if (p + 2 <= d) { // S row k = d - 2 - p
+        const uint32_t k = d - 2 - p;
+        uint64_t *row = S + (uint64_t)k * P.stride;
+        if (k + 1 == d - 1)
+            chain_scan<true>(
+                row, P.stride, P.g[k],
+                [&](uint32_t v) { return (v - fdiv(v, P.div_B) * P.B) == 0 ? 1ull : 0ull; }, part,
+                w, G);
+        else {
+            const uint64_t *nxt = S + (uint64_t)(k + 1) * P.stride;
+            chain_scan<true>(row, P.stride, P.g[k], [&](uint32_t v) { return nxt[v]; }, part, w, G);
+        }
+    } else if (p + 1 == d) { // C row M: the work of a row of each remainder
+        uint64_t *CM = C + (uint64_t)M * P.stride;
+        const uint64_t *SM = S + (uint64_t)M * P.stride;
+        const uint32_t per = (P.stride + G - 1) / G;
+        const uint32_t v0 = w * per, v1 = min(P.stride, v0 + per);
+        for (uint32_t v = v0 + threadIdx.x; v < v1; v += blockDim.x)
+            CM[v] = row_work(P, SM, v, fdiv(v, P.div_G2) + 1, nullptr);
+    } else { // C row k = M - 1 - (p - d)
+        const uint32_t k = M - 1 - (p - d);
+        uint64_t *row = C + (uint64_t)k * P.stride;
+        const uint64_t *nxt = C + (uint64_t)(k + 1) * P.stride;
+        chain_scan<true>(row, P.stride, P.g[k], [&](uint32_t v) { return nxt[v]; }, part, w, G);
+    }
+}
+
 // Total modelled work C[0][n] and element count S[0][n] of each query with
 // tables, for the host to size its slice count and its bins.
 __global__ void fz_batch_totals_kernel(FzBatchBufs B, const uint32_t *ids, uint32_t n)
@@ -2462,14 +2509,21 @@ static void launch_batch_enum(const FzBatchBufs &b, uint32_t nwg, uint32_t lds_b
 }
 
 hipError_t fzk_launch_batch_tables(const FzBatchBufs &b, uint32_t n_tabled,
-                                   const uint32_t *tabled_ids, hipStream_t s)
+                                   const uint32_t *tabled_ids, uint32_t n_small,
+                                   const uint32_t *small_ids, const uint32_t *pass_jobs,
+                                   const uint32_t *pass_off, uint32_t n_pass, hipStream_t s)
 {
     hipLaunchKernelGGL(fz_zero_kernel, dim3(64), dim3(256), 0, s, (uint64_t *)b.res,
                        (uint64_t)b.nq * (sizeof(FzBatchResult) / 8));
     if (b.n_bins)
         hipLaunchKernelGGL(fz_zero_kernel, dim3(256), dim3(256), 0, s, b.bins, b.n_bins);
     if (n_tabled) {
-        hipLaunchKernelGGL(fz_batch_dp_kernel, dim3(n_tabled), dim3(1024), 0, s, b, tabled_ids);
+        if (n_small) // one workgroup per query, every row in turn
+            hipLaunchKernelGGL(fz_batch_dp_kernel, dim3(n_small), dim3(1024), 0, s, b, small_ids);
+        for (uint32_t p = 0; p < n_pass; ++p) // pass by pass, rows shared by workgroups
+            if (pass_off[p + 1] > pass_off[p])
+                hipLaunchKernelGGL(fz_batch_dp_pass_kernel, dim3(pass_off[p + 1] - pass_off[p]),
+                                   dim3(1024), 0, s, b, pass_jobs + 3 * (size_t)pass_off[p], p);
         hipLaunchKernelGGL(fz_batch_totals_kernel, dim3((n_tabled + 255) / 256), dim3(256), 0, s,
                            b, tabled_ids, n_tabled);
     }

@@ -298,3 +298,25 @@ def test_sparse_pairs_in_a_batch(fz, order):
         fz.config_set("walk_order", 0)
     for q, r in zip(qs, res):
         check_against_oracle(q, r)
+
+
+def test_large_queries_in_a_small_batch(fz, batch_result, workload):
+    """A batch of a few queries with large tables (n + 1 > 2^16 entries per
+    row) builds them row by row, each row shared by several workgroups; every
+    result must equal the same query's in the 4096-query batch (one workgroup
+    per query) and its stored count."""
+    qs, res = batch_result
+    idx = [i for i, q in enumerate(qs) if q["n"] + 1 > 1 << 16][:48]
+    assert len(idx) == 48
+    sub = [dict(qs[i]) for i in idx]
+    small = fz.batch(sub)
+    for i, r in zip(idx, small):
+        big, w = res[i], workload[i]
+        assert r["status"] == 0 and big["status"] == 0
+        if qs[i]["mode"] in ("count", "hist"):
+            assert r["count"] == big["count"] == w["count"], qs[i]
+        if qs[i]["mode"] == "hist":
+            assert np.array_equal(r["bins"], big["bins"]), qs[i]
+            assert (r["min_len"], r["max_len"]) == (big["min_len"], big["max_len"])
+        if qs[i]["mode"] == "exists":
+            assert r["found"] == big["found"], qs[i]
