@@ -258,8 +258,9 @@ typedef struct {
 int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
 
 /* Tuning knobs (0 restores the default): "slices_per_wave" (slices cut per
- * resident wavefront), "workgroups_per_cu" (persistent workgroups per compute
- * unit), "work_row", "work_chunk", "work_element" (weights, in 1/64 of a
+ * resident wavefront; default 16 for a single query, 8 for a batch),
+ * "workgroups_per_cu" (persistent workgroups per compute unit; default 8, 4
+ * for a batch), "work_row", "work_chunk", "work_element" (weights, in 1/64 of a
  * wavefront instruction, of a row a_1..a_{d-3}, of a 64-lane chunk of a row
  * and of an element, when slices are cut to equal work), "skip_empty_rows"
  * (0: for sets with few elements per row, skip rows and subtrees that the

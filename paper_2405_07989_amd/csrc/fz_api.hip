@@ -23,6 +23,8 @@ namespace fzh {
 constexpr int kMaxDevices = 64;
 constexpr uint32_t kDefaultSlicesPerWave = 16;
 constexpr uint32_t kDefaultWgPerCu = 8;
+constexpr uint32_t kBatchSlicesPerWave = 8; // batches and the server
+constexpr uint32_t kBatchWgPerCu = 4;
 constexpr uint32_t kMaxSlices = 1u << 22;
 // Least modelled work of a single query's slice (1/64 wave instructions):
 // about a thousand wave instructions, a few microseconds.
@@ -807,10 +809,15 @@ double estimate_work(const FzPlan &P)
     return P.w_row * rows + P.w_chunk * (pref / FZK_WAVE + rows) + P.w_el * el;
 }
 
+// The knobs of a batch (fz_batch and the server).  Their defaults differ
+// from a single query's: the batch walker holds up to 2048 histogram words
+// of LDS per wave, so fewer workgroups fit a CU, and fewer, longer items
+// per wave cost less set-up (mixed 4096-query batch: 84 ms with 16 slices
+// per wave x 8 workgroups per CU, 74 ms with 8 x 4).
 void current_knobs(uint32_t *spw, uint32_t *wgcu)
 {
-    *spw = g_slices_per_wave ? g_slices_per_wave : kDefaultSlicesPerWave;
-    *wgcu = g_wg_per_cu ? g_wg_per_cu : kDefaultWgPerCu;
+    *spw = g_slices_per_wave ? g_slices_per_wave : kBatchSlicesPerWave;
+    *wgcu = g_wg_per_cu ? g_wg_per_cu : kBatchWgPerCu;
 }
 
 hipError_t ensure_pinned(void **p, size_t *cap, size_t bytes)
@@ -1721,14 +1728,18 @@ int fz_autotune(const fz_query *q, uint32_t nq, uint32_t reps, fz_tune_result *o
     };
     fz_tune_result best{};
     int rc = median(0, 0, &best.default_ms);
-    best.slices_per_wave = kDefaultSlicesPerWave;
-    best.workgroups_per_cu = kDefaultWgPerCu;
+    // the defaults timed above: a batch's (nq > 1 runs one fz_batch) or a
+    // single query's
+    const uint32_t def_spw = nq > 1 ? kBatchSlicesPerWave : kDefaultSlicesPerWave;
+    const uint32_t def_wg = nq > 1 ? kBatchWgPerCu : kDefaultWgPerCu;
+    best.slices_per_wave = def_spw;
+    best.workgroups_per_cu = def_wg;
     best.ms = best.default_ms;
     best.candidates = 1;
     for (uint32_t spw : kSpw)
         for (uint32_t wg : kWg) {
             if (rc != FZ_OK) break;
-            if (spw == kDefaultSlicesPerWave && wg == kDefaultWgPerCu) continue;
+            if (spw == def_spw && wg == def_wg) continue;
             double ms = 0;
             rc = median(spw, wg, &ms);
             ++best.candidates;
