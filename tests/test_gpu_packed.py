@@ -138,3 +138,17 @@ def test_packed_walk_at_the_size_limit(fz):
         assert not fz.exists(n, g, int(lens.max()) + 1)
     finally:
         fz.config_set("packed", 0)
+
+
+def test_packed_walk_without_tables(fz):
+    """The packed walk forced on a table-free walk (slices cut by splitWork,
+    no count table: no row is dropped as empty, every row's prefixes are
+    walked)."""
+    try:
+        fz.config_set("packed", 1)
+        fz.config_set("tables", 2)
+        for n, g in CASES:
+            check_order_free(fz, n, g)
+    finally:
+        fz.config_set("packed", 0)
+        fz.config_set("tables", 0)
