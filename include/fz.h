@@ -301,7 +301,11 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * histogram and predicate: the lane prefixes of up to 64 consecutive rows
  * of the deepest row level are walked end to end, 64 at a time; 0: for
  * sparse sets that skip empty rows, 1: always, 2: never; the batch walker
- * walks every order-free consumer packed), "batch_min_item_work" (the least
+ * walks every order-free consumer packed), "empty_row_test" (single queries
+ * with d >= 4 and tables, walked without row skipping, pair table or
+ * packing: 0 or 1, the default: the rows of each block of up to 64 rows of
+ * the deepest row level are tested against the count table, and a row with
+ * no completion is not walked; 2: never), "batch_min_item_work" (the least
  * modelled work of a batch's work item, so that a small batch is not cut
  * into a chip's worth of tiny items; up to 2^30; 0: 2^20 units),
  * "wave_bins32" (single-query histograms of up to ~680 bins: 1, the default:

@@ -101,6 +101,7 @@ uint32_t g_host_threads = 0; // hybrid pool: host worker threads (0: off)
 uint32_t g_host_ppm = 0;     // their share of the work in millionths (0: kHostPpmPerThread each)
 uint32_t g_trailing = 0;     // 1: trailing-index tables (count and store of the block walk)
 uint32_t g_pack_mode = 0;    // packed walk of short rows: 0 by row length, 1 always, 2 never
+uint32_t g_row_test = 0;     // block walk drops rows with no completion: 0/1 with tables, 2 never
 uint64_t g_batch_min_item = 0; // 0: kBatchMinItemWork
 uint32_t g_hist32 = 1;         // single-query histograms: 32-bit LDS bins per wave when they fit
 uint64_t g_hist32_limit = 0;   // their fold threshold in elements (0: 2^31)
@@ -454,6 +455,9 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
     P.trail = (g_trailing && !P.notab && !P.prune && !P.pair && !P.cdv && !P.pack && P.d >= 4 &&
                (P.mode == FZM_COUNT || P.mode == FZM_STORE)) ? 1 : 0;
     P.trail_cap = P.trail && P.mode == FZM_STORE ? kTrailBytes / 12 : 0;
+    // the block walk (d >= 4, no row skipping, pair table or packing) drops
+    // the rows of a block that the count table shows empty
+    P.rowtest = (g_row_test != 2 && !P.notab && !P.prune && !P.pair && !P.pack && P.d >= 4) ? 1 : 0;
 }
 
 // Bytes of each device buffer a single query of plan P needs.
@@ -1661,6 +1665,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "host_share_ppm") == 0 && value <= 500000) g_host_ppm = (uint32_t)value;
     else if (std::strcmp(key, "trailing") == 0 && value <= 1) g_trailing = (uint32_t)value;
     else if (std::strcmp(key, "packed") == 0 && value <= 2) g_pack_mode = (uint32_t)value;
+    else if (std::strcmp(key, "empty_row_test") == 0 && value <= 2) g_row_test = (uint32_t)value;
     else if (std::strcmp(key, "batch_min_item_work") == 0) g_batch_min_item = (uint64_t)value;
     else if (std::strcmp(key, "wave_bins32") == 0 && value <= 1) g_hist32 = (uint32_t)value;
     else if (std::strcmp(key, "wave_bins32_limit") == 0) g_hist32_limit = (uint64_t)value;

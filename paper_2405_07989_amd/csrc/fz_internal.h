@@ -93,6 +93,10 @@ struct FzPlan {
     // d >= 4): the lane prefixes of up to 64 consecutive rows of the deepest
     // row level fill the chunks end to end.
     uint32_t pack;
+    // Block walk with tables (rowtest = 1): the rows of a block whose
+    // remainder has no completion in the count table (S[M][R] = 0) are
+    // dropped before the block is walked.
+    uint32_t rowtest;
     // Single-query histograms with a 32-bit set of bins per wave: a wave
     // folds its set into the workgroup's before it holds this many elements
     // (at most 2^31), and walks a slice of at least this many elements into

@@ -121,7 +121,7 @@ __device__ __forceinline__ uint64_t row_work(const FzPlan &P, const uint64_t *SM
                                              uint32_t t, const uint64_t *PC)
 {
     if (t == 0) return 0;
-    if (P.prune && SM[v] == 0) return P.w_skip; // an empty row is skipped, not walked
+    if ((P.prune || P.rowtest) && SM[v] == 0) return P.w_skip; // an empty row is not walked
     const uint64_t el = SM[v] - (t * (uint64_t)P.G2 <= v ? SM[v - t * P.G2] : 0);
     // lanes visit all t values of x, or with the pair table only the ones
     // with an element
@@ -1039,6 +1039,10 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     (end_here && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
                 // the row's lane prefixes x0, x0 + sx, .., up to xlast (rows of
                 // a stopped walk count in full)
+                // rowtest: a row whose remainder the count table gives no
+                // completion has no element (one vector load tests the
+                // block's rows)
+                if (P.rowtest && has) has = io.S[(uint64_t)MAXM * P.stride + R] != 0;
                 const int32_t v_np = has && xlast >= (int32_t)x0
                                          ? (CDV ? (xlast - (int32_t)x0) / (int32_t)sx
                                                 : xlast - (int32_t)x0) + 1
@@ -1049,8 +1053,12 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 const uint32_t v_Qc = fdiv(v_Rc, P.div_B);
                 const uint32_t v_Pc = v_Rc - v_Qc * P.B;
                 const uint32_t plen0 = plen;
+                // the block's rows that have lane prefixes, in order
+                uint64_t rows_left = __ballot(v_np > 0);
                 uint32_t j = 0;
-                for (; j < nb; ++j) {
+                while (rows_left) {
+                    j = (uint32_t)__builtin_ctzll(rows_left);
+                    rows_left &= rows_left - 1;
                     const int32_t np = (int32_t)__builtin_amdgcn_readlane((uint32_t)v_np, j);
                     const uint32_t Qc = __builtin_amdgcn_readlane(v_Qc, j);
                     const uint32_t Pc = __builtin_amdgcn_readlane(v_Pc, j);
@@ -1124,7 +1132,7 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     }
                     if (done) break;
                 }
-                n_rows += j < nb ? j + 1 : nb;
+                n_rows += done ? j + 1 : nb;
                 if (done || blast) break;
                 // the block's last row, then the next row of the deepest
                 // level (sy further), else of a shallower one
