@@ -313,7 +313,12 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * workgroup's 64-bit bins before they could overflow; 0: all waves add to the
  * workgroup's 64-bit bins), "wave_bins32_limit" (the elements a wave's
  * 32-bit bins may hold before they are folded, at most 2^20 here; 0: 2^31;
- * small values exercise the folding).
+ * small values exercise the folding), "wave_bins32_copies" (interleaved
+ * copies of each wave's 32-bit bins, lane l adding to copy l mod copies, so
+ * that lanes whose runs start in the same bin are served by different LDS
+ * banks: 0, the default: 4, else 2, else 1, while 8 workgroups per CU (or
+ * the "workgroups_per_cu" value) still fit the CU's 160 KiB of LDS; 1, 2 or
+ * 4: that many, as far as a workgroup's 64 KiB allow).
  * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */

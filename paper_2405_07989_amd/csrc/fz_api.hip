@@ -41,6 +41,10 @@ constexpr uint64_t kTrailBytes = 2ull << 30;
 constexpr size_t kLdsHistBudget = 64 * 1024;
 // ... and for the workgroup's set with a 32-bit set per wave beside it.
 constexpr size_t kLdsHist32Budget = 16 * 1024;
+// LDS of a compute unit, shared by its resident workgroups; one workgroup
+// may take at most 64 KiB
+constexpr size_t kLdsPerCu = 160 * 1024;
+constexpr size_t kLdsPerWg = 64 * 1024;
 constexpr size_t kLdsRestabBudget = 16 * 1024; // keeps 8 workgroups per CU
 // per-wave LDS histogram in batches, 8 KB per wave: 1024 64-bit bins, or
 // 2048 32-bit bins for a histogram that needs more
@@ -102,6 +106,7 @@ uint32_t g_host_ppm = 0;     // their share of the work in millionths (0: kHostP
 uint32_t g_trailing = 0;     // 1: trailing-index tables (count and store of the block walk)
 uint32_t g_pack_mode = 0;    // packed walk of short rows: 0 by row length, 1 always, 2 never
 uint32_t g_row_test = 0;     // block walk drops rows with no completion: 0/1 with tables, 2 never
+uint32_t g_hist32_copies = 0; // copies of a wave's 32-bit bins: 0 by LDS room, else 1, 2 or 4
 uint64_t g_batch_min_item = 0; // 0: kBatchMinItemWork
 uint32_t g_hist32 = 1;         // single-query histograms: 32-bit LDS bins per wave when they fit
 uint64_t g_hist32_limit = 0;   // their fold threshold in elements (0: 2^31)
@@ -439,6 +444,19 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
         (size_t)((P.nbins + 2) & ~1u) * (8 + 4 * (FZK_WG / FZK_WAVE)) <= kLdsHist32Budget)
         P.hist_in_lds = 2;
     P.hist32_limit = g_hist32_limit ? g_hist32_limit : (1ull << 31);
+    // interleaved copies of each wave's 32-bit set: 4, else 2, while the
+    // workgroup's LDS leaves room for wgcu workgroups per CU (or the
+    // requested count, within a workgroup's limit)
+    P.hist32_copies = 0;
+    if (P.hist_in_lds == 2) {
+        const uint32_t want = g_hist32_copies ? (uint32_t)__builtin_ctz(g_hist32_copies) : 2u;
+        const size_t room = g_hist32_copies ? kLdsPerWg : std::min(kLdsPerWg, kLdsPerCu / wgcu);
+        for (uint32_t k = want; k > 0; --k) {
+            P.hist32_copies = k;
+            if (fzk_enum_lds_bytes(P) <= room) break;
+            P.hist32_copies = 0;
+        }
+    }
     // hybrid pool (order-free consumers with tables): host threads take the
     // last slices of the work
     P.host_slices = 0;
@@ -1669,6 +1687,9 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "batch_min_item_work") == 0) g_batch_min_item = (uint64_t)value;
     else if (std::strcmp(key, "wave_bins32") == 0 && value <= 1) g_hist32 = (uint32_t)value;
     else if (std::strcmp(key, "wave_bins32_limit") == 0) g_hist32_limit = (uint64_t)value;
+    else if (std::strcmp(key, "wave_bins32_copies") == 0 &&
+             (value == 0 || value == 1 || value == 2 || value == 4))
+        g_hist32_copies = (uint32_t)value;
     else return FZ_EINVAL;
     return FZ_OK;
 }

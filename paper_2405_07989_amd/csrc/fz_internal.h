@@ -102,6 +102,10 @@ struct FzPlan {
     // (at most 2^31), and walks a slice of at least this many elements into
     // the workgroup's set directly.
     uint64_t hist32_limit;
+    // ... and 2^hist32_copies interleaved copies of each wave's 32-bit set:
+    // lane l adds to copy l mod 2^hist32_copies, word bin * 2^hist32_copies
+    // + copy, so lanes whose runs start in the same bin use different banks.
+    uint32_t hist32_copies;
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag

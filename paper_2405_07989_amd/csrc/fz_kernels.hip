@@ -528,6 +528,9 @@ struct WalkIO {
     uint64_t *wbins;    // LDS histogram (difference array), 64-bit bins: the workgroup's
                         // (single query) or this wave's (batch)
     uint32_t *wbins32;  // ... 32-bit bins (batches: every bin of an item stays below 2^31)
+    uint32_t *wbins32l; // single query: this lane's copy of the wave's 32-bit bins (bin b at
+                        // wbins32l[b << w32k])
+    uint32_t w32k;
     uint64_t *gbins;    // the global histogram (bins not in LDS)
     uint32_t *found;    // predicate flag (early exit)
     uint32_t *out;      // store destination, row-major [.][d_user]
@@ -553,7 +556,8 @@ struct WalkOut {
 // step 0 all cnt elements have length len0.  Bins wrap, so negative entries
 // are two's complement: 64-bit bins, or 32-bit ones in a batch, where a bin
 // moves by at most the elements of one work item (< 2^30, checked on the
-// host) and is flushed, sign-extended, after every item.
+// host) and is flushed, sign-extended, after every item.  H32 (a single
+// query): the run goes to the wave's own 32-bit bins, io.wbins32.
 template <bool FIXED, bool H32 = false>
 __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint32_t len0,
                                          uint32_t cnt, int32_t step)
@@ -567,10 +571,10 @@ __device__ __forceinline__ void hist_run(const FzPlan &P, const WalkIO &io, uint
         const uint32_t hi0 = lo + cnt * mag;
         const uint32_t hi = (mag != 0 && hi0 < P.nbins) ? hi0 : P.nbins;
         const uint64_t inc = mag != 0 ? 1ull : (uint64_t)cnt;
-        if (H32 && io.wbins32) { // the wave's own 32-bit bins
-            __hip_atomic_fetch_add(&io.wbins32[lo], (uint32_t)inc, __ATOMIC_RELAXED,
+        if (H32) { // the lane's copy of the wave's 32-bit bins
+            __hip_atomic_fetch_add(&io.wbins32l[lo << io.w32k], (uint32_t)inc, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(&io.wbins32[hi], 0xFFFFFFFFu, __ATOMIC_RELAXED,
+            __hip_atomic_fetch_add(&io.wbins32l[hi << io.w32k], 0xFFFFFFFFu, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         } else if (P.hist_in_lds) { // the workgroup's bins
             __hip_atomic_fetch_add(&io.wbins[lo], inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -712,7 +716,8 @@ __device__ __forceinline__ void count_steps(uint32_t &cnt, int32_t &ad, int32_t 
 // PACK: the packed walk of short rows (count, histogram, predicate): the lane
 // prefixes of up to 64 rows of the deepest row level are laid end to end and
 // walked 64 at a time, so that a chunk is not one row's few prefixes.  (With
-// no row level, M = 0, the one row is walked alone.)
+// no row level, M = 0, the one row is walked alone.)  H32: histogram runs
+// go to the wave's 32-bit bins (io.wbins32 set).
 template <int MAXM, int MODE, bool TLDS, bool PRUNE, bool PAIR, bool FIXED, bool CDV = false,
           bool PACK = false, bool H32 = false>
 __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
@@ -1497,6 +1502,8 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     io.gtab = Bf.restab;
     io.wbins = nullptr;
     io.wbins32 = nullptr;
+    io.wbins32l = nullptr;
+    io.w32k = 0;
     io.gbins = Bf.hist;
     io.found = &Bf.ctl->found;
     io.out = Bf.out;
@@ -1513,28 +1520,38 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
     // every difference entry of a wave's set is bounded by the elements the
     // wave added since its last flush, kept below P.hist32_limit <= 2^31 (a
     // slice's exact element count comes from its ranks).  Private 32-bit sets halve the
-    // atomics' LDS traffic and keep the waves off each other's bins.
+    // atomics' LDS traffic and keep the waves off each other's bins.  A wave's
+    // set has 2^w32k interleaved copies (bin b, copy c at word b 2^w32k + c;
+    // lane l adds to copy l mod 2^w32k): the lanes of a chunk often start
+    // their runs in the same few bins, and same-bank atomics are served one
+    // lane at a time.
     const uint32_t stride32 = (P.nbins + 2) & ~1u; // nbins + 1 words, even
+    const uint32_t w32k = P.hist32_copies;
     if constexpr (MODE == FZM_HIST) {
         if (P.hist_in_lds) { // one set of bins for the workgroup's waves
             io.wbins = (uint64_t *)scratch;
             for (uint32_t i = threadIdx.x; i <= P.nbins; i += blockDim.x) io.wbins[i] = 0;
             if (H32) {
-                io.wbins32 = (uint32_t *)(io.wbins + stride32) + wave * stride32;
-                for (uint32_t i = lane; i <= P.nbins; i += FZK_WAVE) io.wbins32[i] = 0;
+                io.wbins32 = (uint32_t *)(io.wbins + stride32) + ((wave * stride32) << w32k);
+                io.wbins32l = io.wbins32 + (lane & ((1u << w32k) - 1));
+                io.w32k = w32k;
+                for (uint32_t i = lane; i < ((P.nbins + 1) << w32k); i += FZK_WAVE)
+                    io.wbins32[i] = 0;
             }
         }
     }
-    // a wave adds its 32-bit set (sign-extended) into the workgroup's, then
-    // clears it
+    // a wave adds its 32-bit set (each copy sign-extended) into the
+    // workgroup's, then clears it
     auto flush32 = [&]() {
         for (uint32_t i = lane; i <= P.nbins; i += FZK_WAVE) {
-            const int32_t v = (int32_t)io.wbins32[i];
-            if (v != 0) {
-                __hip_atomic_fetch_add(&io.wbins[i], (uint64_t)(int64_t)v, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                io.wbins32[i] = 0;
+            int64_t v = 0;
+            for (uint32_t c = 0; c < (1u << w32k); ++c) {
+                v += (int32_t)io.wbins32[(i << w32k) + c];
+                io.wbins32[(i << w32k) + c] = 0;
             }
+            if (v != 0)
+                __hip_atomic_fetch_add(&io.wbins[i], (uint64_t)v, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     };
     uint64_t wave_el = 0; // elements in the wave's 32-bit set
@@ -1577,10 +1594,16 @@ __global__ void __launch_bounds__(FZK_WG) fz_enum_kernel(FzPlan P, FzBufs Bf)
                 else wave_el += n_s;
             }
         }
+        // (a slice walked into the workgroup's 64-bit set has a walker of
+        // its own, so that the 32-bit one tests nothing per run)
         const WalkOut o =
-            walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2 || VAR == 5), (VAR == 2), true,
-                       (VAR == 3), (VAR == 4 || VAR == 5), H32>(
-                P, M, b0, b0 + NP, Bf.base[s], H32 ? ios : io, lane);
+            (H32 && ios.wbins32 != nullptr)
+                ? walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2 || VAR == 5), (VAR == 2), true,
+                             (VAR == 3), (VAR == 4 || VAR == 5), H32>(P, M, b0, b0 + NP,
+                                                                      Bf.base[s], ios, lane)
+                : walk_slice<M, MODE, TLDS, (VAR == 1 || VAR == 2 || VAR == 5), (VAR == 2), true,
+                             (VAR == 3), (VAR == 4 || VAR == 5), false>(P, M, b0, b0 + NP,
+                                                                        Bf.base[s], io, lane);
         {
             FzSliceRec rec;
             rec.elements = o.elements;
@@ -2214,6 +2237,8 @@ __global__ void __launch_bounds__(FZK_WG)
             io.trail_m = 0;
             io.wbins = nullptr;
             io.wbins32 = nullptr;
+            io.wbins32l = nullptr;
+            io.w32k = 0;
             const uint32_t lds_hist = mode == FZM_HIST ? uni(P.hist_in_lds) : 0u;
             const uint32_t lds_words = lds_hist == 1 ? 2 * P.nbins : P.nbins;
             if (lds_hist) {
@@ -2392,7 +2417,7 @@ size_t fzk_enum_lds_bytes(const FzPlan &p)
     if (p.mode == FZM_HIST && p.hist_in_lds) bytes += ((size_t)p.nbins + 1) * sizeof(uint64_t);
     if (p.mode == FZM_HIST && p.hist_in_lds == 2) // the 64-bit set padded to even words, then 32-bit sets
         bytes += ((size_t)((p.nbins + 2) & ~1u) - (p.nbins + 1)) * sizeof(uint64_t) +
-                 (size_t)waves * ((p.nbins + 2) & ~1u) * sizeof(uint32_t);
+                 ((size_t)waves * ((p.nbins + 2) & ~1u) << p.hist32_copies) * sizeof(uint32_t);
     if (p.mode == FZM_STORE)
         bytes += (size_t)waves * (5 * FZK_WAVE + FZK_WAVE * p.d_user) * sizeof(uint32_t);
     return bytes;

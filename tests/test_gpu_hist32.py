@@ -1,10 +1,11 @@
 """GPU parity of the single-query histogram's per-wave 32-bit bins (knobs
-"wave_bins32", "wave_bins32_limit"): each wave adds its runs to 32-bit bins
-of its own in LDS and folds them, sign-extended, into the workgroup's 64-bit
-bins before they could overflow.  Histograms against the oracle with the
-32-bit bins on and off, and with fold thresholds small enough that waves fold
-after every few slices (and walk slices above the threshold into the 64-bit
-bins directly)."""
+"wave_bins32", "wave_bins32_limit", "wave_bins32_copies"): each wave adds
+its runs to 32-bit bins of its own in LDS (1, 2 or 4 interleaved copies,
+lane l adding to copy l mod copies) and folds them, sign-extended, into the
+workgroup's 64-bit bins before they could overflow.  Histograms against the
+oracle with the 32-bit bins on and off, with each copy count, and with fold
+thresholds small enough that waves fold after every few slices (and walk
+slices above the threshold into the 64-bit bins directly)."""
 import numpy as np
 import pytest
 
@@ -46,12 +47,15 @@ def cases():
     ]
 
 
+@pytest.mark.parametrize("copies", [0, 1, 2, 4], ids=["copies-auto", "copies-1", "copies-2",
+                                                     "copies-4"])
 @pytest.mark.parametrize("on,limit", [(1, 0), (0, 0), (1, 1000), (1, 64), (1, 1)],
                          ids=["default", "off", "fold-1000", "fold-64", "fold-1"])
-def test_histograms_with_wave_bins(fz, on, limit):
+def test_histograms_with_wave_bins(fz, on, limit, copies):
     try:
         fz.config_set("wave_bins32", on)
         fz.config_set("wave_bins32_limit", limit)
+        fz.config_set("wave_bins32_copies", copies)
         for n, g in cases():
             h, lo, hi = fz.length_hist(n, g)
             oh, olo, ohi = oracle_hist(n, g)
@@ -59,14 +63,18 @@ def test_histograms_with_wave_bins(fz, on, limit):
     finally:
         fz.config_set("wave_bins32", 1)
         fz.config_set("wave_bins32_limit", 0)
+        fz.config_set("wave_bins32_copies", 0)
 
 
+@pytest.mark.parametrize("copies", [0, 1, 2, 4], ids=["copies-auto", "copies-1", "copies-2",
+                                                     "copies-4"])
 @pytest.mark.parametrize("limit", [0, 4096], ids=["default", "fold-4096"])
-def test_length_set_with_wave_bins(fz, limit):
+def test_length_set_with_wave_bins(fz, limit, copies):
     """The d = 11 length set (271 bins, 1.0e11 elements)."""
     ls = GOLD["length_set"]
     try:
         fz.config_set("wave_bins32_limit", limit)
+        fz.config_set("wave_bins32_copies", copies)
         h, lo, hi = fz.length_hist(ls["n"], ls["g"])
         want = oracle.dp_hist(ls["n"], ls["g"])
         assert np.array_equal(h, want) and int(h.sum()) == ls["count"]
@@ -74,3 +82,4 @@ def test_length_set_with_wave_bins(fz, limit):
         assert (lo, hi) == (int(nz[0]), int(nz[-1]))
     finally:
         fz.config_set("wave_bins32_limit", 0)
+        fz.config_set("wave_bins32_copies", 0)
