@@ -285,6 +285,7 @@ int make_plan(uint64_t n, const uint32_t *g, uint32_t d, uint32_t mode, FzPlan *
     P->div_B = make_fastdiv(P->B);
     P->div_delta = make_fastdiv(P->delta);
     P->div_G2 = make_fastdiv(P->G2);
+    P->div_D = make_fastdiv(P->D);
     // lanes of a chunk differ by up to 63 G2 in remainder, i.e. by about
     // 63 G2 D / (A B) elements in progression length
     const double spread = 63.0 * P->G2 * P->D / ((double)P->A * P->B);
@@ -392,6 +393,11 @@ void set_variant(FzPlan &P)
     P.cd_sy = (uint32_t)sy;
     P.cd_e3 = (uint32_t)e3;
     P.cd_inv3 = sy > 1 ? modinv((gy / e3) % sy, sy) : 0;
+    P.div_e2 = make_fastdiv(P.cd_e2);
+    P.div_sx = make_fastdiv(P.cd_sx);
+    P.div_D3 = make_fastdiv(P.cd_D3);
+    P.div_e3 = make_fastdiv(P.cd_e3);
+    P.div_sy = make_fastdiv(P.cd_sy);
     P.cdv = 1;
 }
 
@@ -408,6 +414,8 @@ void set_lane_stride(FzPlan &P)
     P.cd_sx = (uint32_t)sx;
     P.cd_e2 = (uint32_t)e2;
     P.cd_inv2 = sx > 1 ? modinv((P.G2 / e2) % sx, sx) : 0;
+    P.div_e2 = make_fastdiv(P.cd_e2);
+    P.div_sx = make_fastdiv(P.cd_sx);
 }
 
 // Slice count, walker grid and walker variant of plan P on a device with

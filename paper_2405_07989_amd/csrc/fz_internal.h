@@ -71,6 +71,9 @@ struct FzPlan {
     uint32_t cdv;
     uint32_t cd_sx, cd_e2, cd_inv2;
     uint32_t cd_D3, cd_sy, cd_e3, cd_inv3;
+    // divisions by D, e2 and sx (the packed walk's lane stride too), D3, e3
+    // and sy; sx, sy < 2^16, so the residue products fit 32 bits
+    FzFastDiv div_D, div_e2, div_sx, div_D3, div_e3, div_sy;
     // Table-free walk (notab = 1; count, histogram and predicate only): no
     // count or work table; the W slices are cut by repeated splitWork
     // (Sec. 4, Alg. 4.1) from the whole set, and no slice is checked

@@ -33,6 +33,12 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t x, const FzFastDiv &f)
     return (t + ((x - t) >> f.s1)) >> f.s2;
 }
 
+// x mod f.d, exact for every x < 2^32.
+__device__ __forceinline__ uint32_t fmod32(uint32_t x, const FzFastDiv &f)
+{
+    return x - fdiv(x, f) * f.d;
+}
+
 // A lane's 64-bit value read by the whole wave (a wave-uniform result).
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane)
 {
@@ -983,10 +989,10 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     // the first row at or after ay whose remainder is a
                     // multiple of D3: y = ay + dy with dy (gy / e3) = (R0 mod
                     // D3) / e3 (mod sy); none when e3 does not divide R0
-                    const uint32_t r3 = R0 % P.cd_D3;
-                    bool any = r3 % P.cd_e3 == 0;
-                    const uint32_t dy =
-                        any ? (uint32_t)((uint64_t)(r3 / P.cd_e3) * P.cd_inv3 % sy) : 0u;
+                    const uint32_t r3 = fmod32(R0, P.div_D3);
+                    const uint32_t q3 = fdiv(r3, P.div_e3);
+                    bool any = r3 == q3 * P.cd_e3;
+                    const uint32_t dy = any ? fmod32(q3 * P.cd_inv3, P.div_sy) : 0u;
                     any = any && (uint64_t)dy * gy <= R0 && (!upper_eq || ay + dy <= e[MAXM - 1]);
                     if (!any) {
                         // nothing left on this level: the slice's end when its
@@ -1035,10 +1041,11 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 bool has = in;
                 if constexpr (CDV) {
                     // the row's first x at or after x0 with x G2 = R (mod D)
-                    const uint32_t r2 = R % P.D;
-                    has = has && r2 % P.cd_e2 == 0;
-                    const uint32_t xst = (uint32_t)((uint64_t)(r2 / P.cd_e2) * P.cd_inv2 % sx);
-                    x0 += (xst + sx - x0 % sx) % sx;
+                    const uint32_t r2 = fmod32(R, P.div_D);
+                    const uint32_t q2 = fdiv(r2, P.div_e2);
+                    has = has && r2 == q2 * P.cd_e2;
+                    const uint32_t xst = fmod32(q2 * P.cd_inv2, P.div_sx);
+                    x0 += fmod32(xst + sx - fmod32(x0, P.div_sx), P.div_sx);
                 }
                 const int32_t xlast =
                     (end_here && lane + 1 == nb) ? xe - 1 : (int32_t)fdiv(R, P.div_G2);
@@ -1224,11 +1231,11 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                     // only x with x G2 = R (mod D) can have an element: none
                     // when e2 does not divide R, else every sxp-th x from
                     // the first at or after x0
-                    const uint32_t r2 = R % P.D;
-                    const uint32_t xst =
-                        (uint32_t)((uint64_t)(r2 / P.cd_e2) * P.cd_inv2 % sxp);
-                    x0 += (int32_t)((xst + sxp - (uint32_t)x0 % sxp) % sxp);
-                    has = r2 % P.cd_e2 == 0 && xl_row >= x0;
+                    const uint32_t r2 = fmod32(R, P.div_D);
+                    const uint32_t q2 = fdiv(r2, P.div_e2);
+                    const uint32_t xst = fmod32(q2 * P.cd_inv2, P.div_sx);
+                    x0 += (int32_t)fmod32(xst + sxp - fmod32((uint32_t)x0, P.div_sx), P.div_sx);
+                    has = r2 == q2 * P.cd_e2 && xl_row >= x0;
                 }
                 if constexpr (PRUNE)
                     if (has) has = io.S[(uint64_t)M * P.stride + R] != 0;
