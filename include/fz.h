@@ -318,7 +318,12 @@ int fz_last_slices(fz_slice_info *out, uint32_t cap, uint32_t *n_slices);
  * that lanes whose runs start in the same bin are served by different LDS
  * banks: 0, the default: 4, else 2, else 1, while 8 workgroups per CU (or
  * the "workgroups_per_cu" value) still fit the CU's 160 KiB of LDS; 1, 2 or
- * 4: that many, as far as a workgroup's 64 KiB allow).
+ * 4: that many, as far as a workgroup's 64 KiB allow), "short_last_slices"
+ * (count, histogram and predicate of a single query cut into 64 or more
+ * slices without host threads: 0 or 1, the default: the last quarter of the
+ * slices carries a quarter of the modelled work of each of the others, so
+ * that the slices still walked after the last one was taken are short; 2:
+ * equal slices).
  * FZ_EINVAL for an
  * unknown key or a value outside its range (0..2^20 for the sizes and
  * weights).  Results never depend on the knobs. */

@@ -107,6 +107,7 @@ uint32_t g_trailing = 0;     // 1: trailing-index tables (count and store of the
 uint32_t g_pack_mode = 0;    // packed walk of short rows: 0 by row length, 1 always, 2 never
 uint32_t g_row_test = 0;     // block walk drops rows with no completion: 0/1 with tables, 2 never
 uint32_t g_hist32_copies = 0; // copies of a wave's 32-bit bins: 0 by LDS room, else 1, 2 or 4
+uint32_t g_guided = 0;       // short last slices of a single query: 0/1 on, 2 off
 uint64_t g_batch_min_item = 0; // 0: kBatchMinItemWork
 uint32_t g_hist32 = 1;         // single-query histograms: 32-bit LDS bins per wave when they fit
 uint64_t g_hist32_limit = 0;   // their fold threshold in elements (0: 2^31)
@@ -484,6 +485,9 @@ void plan_launch(int cus, FzPlan &P, Launch &L)
     // the block walk (d >= 4, no row skipping, pair table or packing) drops
     // the rows of a block that the count table shows empty
     P.rowtest = (g_row_test != 2 && !P.notab && !P.prune && !P.pair && !P.pack && P.d >= 4) ? 1 : 0;
+    // short last slices for the order-free consumers (a store's slices
+    // each stage and write their own rows: more of them cost more)
+    P.guided = (g_guided != 2 && P.mode != FZM_STORE) ? 1 : 0;
 }
 
 // Bytes of each device buffer a single query of plan P needs.
@@ -1695,6 +1699,7 @@ int fz_config_set(const char *key, int64_t value)
     else if (std::strcmp(key, "batch_min_item_work") == 0) g_batch_min_item = (uint64_t)value;
     else if (std::strcmp(key, "wave_bins32") == 0 && value <= 1) g_hist32 = (uint32_t)value;
     else if (std::strcmp(key, "wave_bins32_limit") == 0) g_hist32_limit = (uint64_t)value;
+    else if (std::strcmp(key, "short_last_slices") == 0 && value <= 2) g_guided = (uint32_t)value;
     else if (std::strcmp(key, "wave_bins32_copies") == 0 &&
              (value == 0 || value == 1 || value == 2 || value == 4))
         g_hist32_copies = (uint32_t)value;

@@ -109,6 +109,9 @@ struct FzPlan {
     // lane l adds to copy l mod 2^hist32_copies, word bin * 2^hist32_copies
     // + copy, so lanes whose runs start in the same bin use different banks.
     uint32_t hist32_copies;
+    // Single-query slice cut: the last quarter of the slices is cut a
+    // quarter of the size of the others (guided = 1).
+    uint32_t guided;
 };
 
 // Control block in device memory.  The slice cursor and the early-exit flag

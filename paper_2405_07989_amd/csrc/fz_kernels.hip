@@ -445,10 +445,16 @@ __device__ uint64_t slice_bound(const FzPlan &P, const uint64_t *S, const uint64
         Wtot = acc + row_work(P, SM, v, x + 1, PC);
     }
     // work rank of bound j: W equal parts, or, with a host share, W - T
-    // equal parts of the device's work and T of the host's
+    // equal parts of the device's work and T of the host's.  guided: the
+    // last W/4 slices take a quarter of the work of each of the others, so
+    // that the slices still walked after the cursor has run out are short.
     uint64_t rc;
     const uint32_t T = P.host_slices;
-    if (T == 0) {
+    if (T == 0 && P.guided && W >= 64) {
+        const uint64_t L = W / 4, U = 4 * (uint64_t)(W - L) + L;
+        const uint64_t u = j <= W - L ? 4 * (uint64_t)j : 4 * (uint64_t)(W - L) + (j - (W - L));
+        rc = (Wtot / U) * u + ((Wtot % U) * u) / U;
+    } else if (T == 0) {
         rc = (Wtot / W) * j + ((Wtot % W) * j) / W;
     } else {
         const uint32_t Wd = W - T;

@@ -5,7 +5,8 @@ the test on (the default with tables) and off, in both walk orders, with
 slices cut at every modelled-work boundary (slices that begin and end inside
 rows, some of them empty), with the trailing-index tables and with the
 variant walk; on the benchmark set, the walker statistics: the same rows and
-elements, fewer lane prefixes."""
+elements, fewer lane prefixes.  Also the slice cut with short last slices
+(knob "short_last_slices") on and off."""
 import numpy as np
 import pytest
 
@@ -129,3 +130,14 @@ def test_row_test_benchmark_statistics(fz):
     assert on["elements"] == off["elements"] == big["count"]
     assert on["rows"] == off["rows"]
     assert on["prefixes"] < 0.3 * off["prefixes"]
+
+
+@pytest.mark.parametrize("short", [0, 2], ids=["short-last", "equal"])
+def test_short_last_slices(fz, short):
+    """Knob "short_last_slices": the last quarter of the slices is cut a
+    quarter of the size of the others (or all equal); results are those of
+    the oracle either way, with many slices per query (min_slice_work 1)."""
+    def run():
+        for n, g in CASES[-8:]:
+            check_all(fz, n, g)
+    with_knobs(fz, {"short_last_slices": short, "min_slice_work": 1}, run)
