@@ -316,13 +316,14 @@ def measure_served(fz, torch, n_single=1000):
             q["max_tuples"] = counts[i]
     torch.cuda.synchronize()
 
+    def result_ok(q, r, c):
+        if q["mode"] == "store":
+            return r["status"] == 0 and r["total"] == c == r["written"]
+        return r["status"] == 0 and (r["count"] == c or (q["mode"] == "exists" and r["found"]))
+
     def check(results, label):
         for i, (q, r) in enumerate(zip(stream, results)):
-            ok = r["status"] == 0 and (r["count"] == counts[i] or
-                                       (q["mode"] == "exists" and r["found"]))
-            if q["mode"] == "store":
-                ok = r["status"] == 0 and r["total"] == counts[i] == r["written"]
-            if not ok:
+            if not result_ok(q, r, counts[i]):
                 raise RuntimeError(f"served ({label}): wrong result for query {i} {q}: {r}")
 
     _serve(fz, stream[:500])  # warm-up: buffers of the slots
@@ -365,6 +366,21 @@ def measure_served(fz, torch, n_single=1000):
                                    "p50_us": percentile(lat, 0.5) * 1e6,
                                    "p99_us": percentile(lat, 0.99) * 1e6}
     out["speedup_vs_one_launch_per_query"] = qps / single_qps
+    # one fz_batch call per query (a batch of one), the same queries
+    lat_b = []
+    t0 = time.perf_counter()
+    for i, q in enumerate(stream[:n_single]):
+        t1 = time.perf_counter()
+        r = fz.batch([q])[0]
+        lat_b.append(time.perf_counter() - t1)
+        if not result_ok(q, r, counts[i]):
+            raise RuntimeError(f"batch of one: wrong result for query {i} {q}: {r}")
+    batch1_qps = n_single / (time.perf_counter() - t0)
+    log(f"one fz_batch call per query: {batch1_qps:.0f} queries/s")
+    out["one_batch_call_per_query"] = {"queries": n_single, "queries_per_s": batch1_qps,
+                                       "p50_us": percentile(lat_b, 0.5) * 1e6,
+                                       "p99_us": percentile(lat_b, 0.99) * 1e6}
+    out["speedup_vs_one_batch_call_per_query"] = qps / batch1_qps
     out["workload"] = ("20000 queries drawn as the batch, 20% store queries (|Z| <= 1e7, "
                        "written to device buffers allocated before timing), up to 4 launches "
                        "in flight")
