@@ -1061,10 +1061,11 @@ __device__ __forceinline__ WalkOut walk_slice(const FzPlan &P, const uint32_t M,
                 // completion has no element (one vector load tests the
                 // block's rows)
                 if (P.rowtest && has) has = io.S[(uint64_t)MAXM * P.stride + R] != 0;
-                const int32_t v_np = has && xlast >= (int32_t)x0
-                                         ? (CDV ? (xlast - (int32_t)x0) / (int32_t)sx
-                                                : xlast - (int32_t)x0) + 1
-                                         : 0;
+                const int32_t v_np =
+                    has && xlast >= (int32_t)x0
+                        ? (CDV ? (int32_t)fdiv((uint32_t)(xlast - (int32_t)x0), P.div_sx)
+                               : xlast - (int32_t)x0) + 1
+                        : 0;
                 lane_pref64 += (uint32_t)v_np;
                 const uint32_t v_x0 = x0;
                 const uint32_t v_Rc = R - x0 * P.G2;
